@@ -1,0 +1,52 @@
+"""Pins of the oracle's coupled two-phase step (Secs. 2.1-2.3).
+
+Laplace's law for a static droplet: the pressure jump p(in) - p(out) equals
+2 sigma / R_eff (R_eff from the droplet volume) up to the interface-width
+discretisation error, for density ratios 1 and 10; the phase volume is
+conserved to round-off and the spurious currents stay small.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_01126_amd import inputs as I
+
+SIGMA = 0.01
+
+
+def _droplet_run(n, R, ratio, steps, inside=1.0):
+    phi0, _ = I.droplet((n, n, n), R, 4.0, seed=1, inside=inside)
+    o = O.Oracle((n, n, n), 1.0, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=SIGMA, mobility=0.05,
+                 width=4.0, p0=0.0)
+    r0 = o.reduce()
+    o.step(steps)
+    m = o.moments()
+    r1 = o.reduce()
+    phi, p = m["phi"], m["p"]
+    vin = phi.sum() if inside == 1.0 else (1 - phi).sum()
+    reff = (3 * vin / (4 * math.pi)) ** (1 / 3)
+    if inside == 1.0:
+        dp = p[phi > 0.99].mean() - p[phi < 0.01].mean()
+    else:
+        dp = p[phi < 0.01].mean() - p[phi > 0.99].mean()
+    return dp / (2 * SIGMA / reff), r0, r1, np.abs(m["u"]).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("ratio", [1.0, 10.0])
+def test_laplace_law_droplet(ratio):
+    q, r0, r1, umax = _droplet_run(32, 8.0, ratio, 1000)
+    assert q == pytest.approx(1.0, abs=0.03)
+    assert abs(r1[0] - r0[0]) / r0[0] < 1e-13      # phase volume
+    assert umax < 1e-4                              # spurious currents
+    assert r1[9] == 0
+
+
+def test_surface_tension_sign_and_short_run_conservation():
+    """A short run: the pressure inside a phi = 1 droplet rises above the outside
+    and sum phi is unchanged to round-off."""
+    q, r0, r1, umax = _droplet_run(24, 6.0, 10.0, 150)
+    assert q > 0.3
+    assert abs(r1[0] - r0[0]) / r0[0] < 1e-14
