@@ -1,0 +1,139 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice update library (liblbm.so).
+ *
+ * One time step of the method of accLB (arXiv 2505.01126, Sec. 2):
+ *   - D3Q27 populations, pull-streamed and rebuilt by the regularised collision
+ *     of Eqs. (6)-(7) from p*, u and the Hermite coefficient a^(2), so every
+ *     site writes only its own slots (Sec. 3, thread-safe formulation);
+ *   - Guo forcing, Eq. (5), with the total force of Eq. (8): surface tension
+ *     F^s, pressure correction F^p, viscous correction F^nu, plus an optional
+ *     time-independent body force (Sec. 5.1);
+ *   - the conservative Allen-Cahn phase field, Eq. (3), advected with WENO-5
+ *     and diffused/sharpened with the lattice stencils of Sec. 2.3, on its own
+ *     array, coupled to the same kernel.
+ *
+ * Conventions
+ *   Grid: periodic nx * ny * nz, site s = (z * ny + y) * nx + x, N = nx*ny*nz.
+ *   Vector fields are component major (SoA): v[c * N + s], c = x, y, z.
+ *   Lattice units: dx = dt = 1, c_s^2 = 1/3, nu = c_s^2 (tau - 1/2).
+ *   All device pointers belong to the caller; the library never allocates or
+ *   frees device memory.  Every call is asynchronous on the stream given to
+ *   lbm_init / lbm_set_stream unless stated otherwise.
+ *   One handle per stream; a handle is not thread safe.
+ *
+ * Errors: every int-returning call gives LBM_OK (0) or a negative code;
+ * lbm_last_error() holds the text of the latest failure on a handle.  Nothing
+ * throws across the ABI.  Non-finite fields are reported by lbm_reduce
+ * (out[9]), not as an error code.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+#define LBM_NRED 10          /* number of lbm_reduce outputs */
+#define LBM_MAX_MODES 64     /* forcing table rows */
+#define LBM_MLP_NPARAM 6212  /* 27*64+64 + 64*64+64 + 64*4+4 */
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,   /* bad dimensions or parameters */
+    LBM_ENOSPACE = -2, /* workspace smaller than lbm_workspace_bytes() */
+    LBM_EHIP = -3,     /* a HIP runtime error (text in lbm_last_error) */
+    LBM_ESTATE = -4    /* call not valid in the handle's state */
+};
+
+/* population storage: FP32, or FP16 / BF16 holding h_i = f_i / w_i - P0
+ * (arithmetic is FP32 in every mode; FP32 storage holds the same shifted h_i) */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
+
+/* curvature used by the surface-tension force */
+enum { LBM_CURV_FD = 0, LBM_CURV_MLP = 1 };
+
+typedef struct lbm_handle lbm_handle;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* each >= 8 */
+    int32_t storage;     /* LBM_STORE_* */
+    int32_t two_phase;   /* 0: single phase (rho = rho_l, no phase field), 1: coupled Allen-Cahn */
+    int32_t curv_mode;   /* LBM_CURV_*; LBM_CURV_MLP needs lbm_set_mlp before stepping */
+    double tau;          /* relaxation time > 1/2 (omega = 1/tau, Sec. 2.2) */
+    double rho_l, rho_g; /* densities of the phi = 1 and phi = 0 phases, > 0 */
+    double sigma;        /* surface tension (gamma of Sec. 2.3) */
+    double mobility;     /* interface diffusivity D of Eq. (3) */
+    double width;        /* interface width delta; kappa = 4 D / delta */
+    double p0;           /* pressure gauge P0: storage shift and the p* used when no initial p* is given */
+    int32_t n_modes;     /* forcing rows, 0 .. LBM_MAX_MODES */
+    int32_t zchunk;      /* z planes per workgroup (0 = library default) */
+    const double *modes; /* HOST table [n_modes][9]: kx ky kz Re(Ax) Im(Ax) Re(Ay) Im(Ay) Re(Az) Im(Az);
+                            integer wave numbers with |kz| <= 2; body acceleration
+                            a(x) = sum_m Re(A_m exp(2 pi i (kx x/nx + ky y/ny + kz z/nz)));
+                            read during lbm_init only */
+    double mlp_k_lo;     /* MLP blend ramp on |K_FD| (defaults 0.4 .. 0.6 when both are 0) */
+    double mlp_k_hi;
+} lbm_config;
+
+/* LBM_ABI_VERSION of the loaded library. */
+int lbm_abi_version(void);
+
+/* Device bytes the caller must provide to lbm_init for this configuration;
+ * 0 when the configuration is invalid. */
+size_t lbm_workspace_bytes(const lbm_config *cfg);
+
+/* Create a handle and write the initial state into the workspace.
+ *   d_ws     device buffer of ws_bytes >= lbm_workspace_bytes(cfg), 256-byte
+ *            aligned, owned by the caller and kept alive for the handle's life;
+ *            it holds the whole solver state (populations, phi, u).
+ *   d_phi0   device FP64 [N], phi at t = 0 (required when two_phase, else ignored)
+ *   d_u0     device FP64 [3N] SoA velocity at t = 0, or NULL for rest
+ *   d_pstar0 device FP64 [N] p* at t = 0, or NULL for p* = P0 everywhere
+ *   stream   hipStream_t (NULL = default stream); the inputs may be released
+ *            once the stream has passed this call.
+ * Populations start at f^eq(p*, u) plus the regularised non-equilibrium part
+ * with a^(2) = -c_s^2 tau (grad u + grad u^T) (Sec. 2.2).
+ * Returns LBM_EINVAL (bad config or NULL d_phi0 with two_phase),
+ * LBM_ENOSPACE, LBM_EHIP. */
+int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_bytes, const double *d_phi0,
+             const double *d_u0, const double *d_pstar0, void *stream);
+
+/* Advance nsteps >= 0 time steps (one fused kernel launch per step). */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Fields at the current time n, written to caller device buffers; any pointer
+ * may be NULL.  rho and p = p* rho c_s^2 are FP32 [N], u FP32 [3N] SoA with
+ * u = j + a/2 (Sec. 2.2), phi FP64 [N]. */
+int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_phi);
+
+/* Global FP64 statistics at time n (deterministic order of summation):
+ *   out[0] sum phi, [1] sum rho, [2] sum p*, [3..5] sum rho u, [6] 1/2 sum rho |u|^2,
+ *   [7] max |u|, [8] max overshoot of phi outside [0, 1], [9] sites with a non-finite
+ *   p*, u or phi.
+ * out_is_host = 1: out is host memory and the call waits for the stream;
+ * out_is_host = 0: out is device memory, written asynchronously. */
+int lbm_reduce(lbm_handle *h, double *out, int out_is_host);
+
+/* Steps taken since lbm_init. */
+int64_t lbm_steps_done(const lbm_handle *h);
+
+/* Change the stream later calls run on. */
+int lbm_set_stream(lbm_handle *h, void *stream);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+int lbm_destroy(lbm_handle *h);
+
+/* Static text for an error code. */
+const char *lbm_strerror(int code);
+
+/* Text of the latest failure on h (empty string when none). */
+const char *lbm_last_error(const lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,227 @@
+"""ctypes binding of liblbm.so (include/lbm.h): argument marshalling only.
+
+Every step of the lattice update runs in the library's HIP kernels; PyTorch
+supplies device memory (the workspace and the field buffers) and the stream.
+There is no fallback: a missing library or a missing GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_ESTATE = 0, -1, -2, -3, -4
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+CURV = {"fd": 0, "mlp": 1}
+NRED = 10
+MAX_MODES = 64
+MLP_NPARAM = 6212
+REDUCE_NAMES = ("sum_phi", "sum_rho", "sum_pstar", "sum_rho_ux", "sum_rho_uy", "sum_rho_uz", "kinetic",
+                "max_u", "phi_overshoot", "nonfinite")
+
+
+class LbmError(RuntimeError):
+    pass
+
+
+class lbm_config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("storage", C.c_int32), ("two_phase", C.c_int32), ("curv_mode", C.c_int32),
+        ("tau", C.c_double), ("rho_l", C.c_double), ("rho_g", C.c_double),
+        ("sigma", C.c_double), ("mobility", C.c_double), ("width", C.c_double), ("p0", C.c_double),
+        ("n_modes", C.c_int32), ("zchunk", C.c_int32), ("modes", C.POINTER(C.c_double)),
+        ("mlp_k_lo", C.c_double), ("mlp_k_hi", C.c_double),
+    ]
+
+
+_lib = None
+
+SYMBOLS = {
+    "lbm_abi_version": (C.c_int, []),
+    "lbm_workspace_bytes": (C.c_size_t, [C.POINTER(lbm_config)]),
+    "lbm_init": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(lbm_config), C.c_void_p, C.c_size_t, C.c_void_p,
+                           C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lbm_steps_done": (C.c_int64, [C.c_void_p]),
+    "lbm_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_strerror": (C.c_char_p, [C.c_int]),
+    "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+
+def load_library(path=LIBPATH):
+    """Load liblbm.so and declare every exported symbol (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LbmError(f"{path} is missing: build it with `python -m paper_2505_01126_amd.build` "
+                       "(or __graft_entry__.build())")
+    L = C.CDLL(path)
+    for name, (res, args) in SYMBOLS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, handle=None, what=""):
+    if rc != LBM_OK:
+        L = load_library()
+        msg = L.lbm_last_error(handle).decode() if handle is not None else L.lbm_last_error(None).decode()
+        raise LbmError(f"{what}: {L.lbm_strerror(rc).decode()} ({rc}): {msg}")
+
+
+def make_config(shape, tau, two_phase=False, storage="f32", rho_l=1.0, rho_g=1.0, sigma=0.0, mobility=0.0,
+                width=4.0, p0=1.0, modes=None, zchunk=0, curv_mode="fd", mlp_k_lo=0.0, mlp_k_hi=0.0):
+    """Build an lbm_config; returns (config, keepalive) where keepalive owns the mode table."""
+    nz, ny, nx = shape
+    tab = None if modes is None or len(modes) == 0 else np.ascontiguousarray(modes, dtype=np.float64)
+    cfg = lbm_config(nx, ny, nz, STORAGE[storage], int(bool(two_phase)), CURV[curv_mode], float(tau),
+                     float(rho_l), float(rho_g), float(sigma), float(mobility), float(width), float(p0),
+                     0 if tab is None else len(tab), int(zchunk),
+                     None if tab is None else tab.ctypes.data_as(C.POINTER(C.c_double)),
+                     float(mlp_k_lo), float(mlp_k_hi))
+    return cfg, tab
+
+
+def lbm_abi_version():
+    return load_library().lbm_abi_version()
+
+
+def lbm_workspace_bytes(cfg):
+    return load_library().lbm_workspace_bytes(C.byref(cfg))
+
+
+def lbm_init(cfg, d_ws, ws_bytes, d_phi0, d_u0, d_pstar0, stream):
+    h = C.c_void_p()
+    rc = load_library().lbm_init(C.byref(h), C.byref(cfg), d_ws, ws_bytes, d_phi0, d_u0, d_pstar0, stream)
+    _check(rc, None, "lbm_init")
+    return h
+
+
+def lbm_step(h, nsteps):
+    _check(load_library().lbm_step(h, int(nsteps)), h, "lbm_step")
+
+
+def lbm_moments(h, d_rho, d_p, d_u, d_phi):
+    _check(load_library().lbm_moments(h, d_rho, d_p, d_u, d_phi), h, "lbm_moments")
+
+
+def lbm_reduce(h, out, out_is_host):
+    _check(load_library().lbm_reduce(h, out, int(out_is_host)), h, "lbm_reduce")
+
+
+def lbm_steps_done(h):
+    return load_library().lbm_steps_done(h)
+
+
+def lbm_set_stream(h, stream):
+    _check(load_library().lbm_set_stream(h, stream), h, "lbm_set_stream")
+
+
+def lbm_destroy(h):
+    load_library().lbm_destroy(h)
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise LbmError("no GPU visible: the lattice library runs only on the MI355X")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One simulation: owns the workspace tensor and the library handle.
+
+    shape = (nz, ny, nx).  phi0 [nz,ny,nx], u0 [3,nz,ny,nx], pstar0 [nz,ny,nx]
+    are numpy or torch arrays (float64 on the device after conversion).
+    """
+
+    def __init__(self, shape, tau, phi0=None, u0=None, pstar0=None, two_phase=None, storage="f32", rho_l=1.0,
+                 rho_g=1.0, sigma=0.0, mobility=0.0, width=4.0, p0=1.0, modes=None, zchunk=0, curv_mode="fd",
+                 mlp_k_lo=0.0, mlp_k_hi=0.0, device="cuda:0"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = tuple(int(s) for s in shape)
+        nz, ny, nx = self.shape
+        self.N = nx * ny * nz
+        if two_phase is None:
+            two_phase = phi0 is not None
+        self.two_phase = bool(two_phase)
+        self.cfg, self._tab = make_config(self.shape, tau, self.two_phase, storage, rho_l, rho_g, sigma, mobility,
+                                          width, p0, modes, zchunk, curv_mode, mlp_k_lo, mlp_k_hi)
+        nbytes = lbm_workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise LbmError("invalid configuration")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+        def dev(a, n):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a)
+            t = t.to(device=self.device, dtype=torch.float64).contiguous()
+            if t.numel() != n:
+                raise LbmError(f"input has {t.numel()} values, expected {n}")
+            return t
+
+        phi = dev(phi0, self.N) if self.two_phase else None
+        u = dev(u0, 3 * self.N)
+        ps = dev(pstar0, self.N)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = lbm_init(self.cfg, C.c_void_p(self.ws.data_ptr()), nbytes, _ptr(phi), _ptr(u), _ptr(ps),
+                          C.c_void_p(self.stream.cuda_stream))
+        self.stream.synchronize()  # the inputs may be released after this
+        self.ws_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    @property
+    def steps(self):
+        return lbm_steps_done(self.h)
+
+    def moments(self):
+        """Fields at the current time as device tensors: rho, p (fp32), u [3,...] (fp32), phi (fp64)."""
+        torch = self.torch
+        rho = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        p = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float32, device=self.device)
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        lbm_moments(self.h, _ptr(rho), _ptr(p), _ptr(u), _ptr(phi))
+        return {"rho": rho, "p": p, "u": u, "phi": phi}
+
+    def reduce(self):
+        """The ten FP64 global statistics at the current time (host numpy array)."""
+        out = np.zeros(NRED)
+        lbm_reduce(self.h, out.ctypes.data_as(C.c_void_p), 1)
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every entry point include/lbm.h declares;
+host-side validation runs without a GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2505_01126_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load_library()
+    names = _declared()
+    assert "lbm_init" in names and "lbm_step" in names and "lbm_moments" in names and "lbm_reduce" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(lbm.SYMBOLS)
+
+
+def test_abi_version_and_constants():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    ver = int(re.search(r"#define LBM_ABI_VERSION (\d+)", text).group(1))
+    assert lbm.lbm_abi_version() == ver
+    assert int(re.search(r"#define LBM_NRED (\d+)", text).group(1)) == lbm.NRED
+    assert int(re.search(r"#define LBM_MLP_NPARAM (\d+)", text).group(1)) == lbm.MLP_NPARAM
+    assert C.sizeof(lbm.lbm_config) == 112
+
+
+def test_workspace_bytes_counts_state():
+    cfg, _ = lbm.make_config((64, 64, 64), 0.8)
+    one = lbm.lbm_workspace_bytes(cfg)
+    N = 64 ** 3
+    assert one >= 2 * 27 * 4 * N
+    cfg2, _ = lbm.make_config((64, 64, 64), 0.8, two_phase=True, storage="f16")
+    two = lbm.lbm_workspace_bytes(cfg2)
+    assert two >= 2 * 27 * 2 * N + 2 * 8 * N + 2 * 12 * N
+    assert two < 2 * 27 * 2 * N + 2 * 8 * N + 2 * 12 * N + (1 << 20)
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)), dict(tau=0.8, storage="f16",
+                                                                                       modes=[[0, 0, 3] + [0] * 6])])
+def test_invalid_configs_rejected_on_host(kw):
+    shape = kw.pop("shape", (16, 16, 16))
+    tau = kw.pop("tau")
+    cfg, keep = lbm.make_config(shape, tau, **kw)
+    assert lbm.lbm_workspace_bytes(cfg) == 0
+    h = C.c_void_p()
+    rc = lbm.load_library().lbm_init(C.byref(h), C.byref(cfg), None, 0, None, None, None, None)
+    assert rc == lbm.LBM_EINVAL
+    assert lbm.load_library().lbm_last_error(None).decode()
+
+
+def test_strerror_texts():
+    L = lbm.load_library()
+    for code in (0, -1, -2, -3, -4):
+        assert L.lbm_strerror(code).decode()
