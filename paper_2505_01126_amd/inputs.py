@@ -22,6 +22,7 @@ argument 2d/delta (the exact steady solution of Eq. (3) for kappa = 4D/delta).
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -179,26 +180,33 @@ def solenoidal_field(shape, rms=0.02, k0=4.0, seed=0):
     """
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
-    kz = np.fft.fftfreq(nz) * nz
-    ky = np.fft.fftfreq(ny) * ny
-    kx = np.fft.rfftfreq(nx) * nx
-    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    KZ = (np.fft.fftfreq(nz) * nz)[:, None, None]
+    KY = (np.fft.fftfreq(ny) * ny)[None, :, None]
+    KX = (np.fft.rfftfreq(nx) * nx)[None, None, :]
     K2 = KX * KX + KY * KY + KZ * KZ
     K = np.sqrt(K2)
     with np.errstate(divide="ignore", invalid="ignore"):
         amp = np.where(K > 0, np.sqrt(K ** 4 * np.exp(-2.0 * (K / k0) ** 2) / np.maximum(K2, 1.0)), 0.0)
+    del K
     spec = []
     for _ in range(3):
-        spec.append((rng.standard_normal(K.shape) + 1j * rng.standard_normal(K.shape)) * amp)
-    spec = np.array(spec)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        kdotv = (KX * spec[0] + KY * spec[1] + KZ * spec[2]) / np.where(K2 > 0, K2, 1.0)
+        spec.append((rng.standard_normal(amp.shape) + 1j * rng.standard_normal(amp.shape)) * amp)
+    del amp
+    inv = np.where(K2 > 0, 1.0 / np.where(K2 > 0, K2, 1.0), 0.0)
+    kdotv = (KX * spec[0] + KY * spec[1] + KZ * spec[2]) * inv
     spec[0] -= KX * kdotv
     spec[1] -= KY * kdotv
     spec[2] -= KZ * kdotv
-    u = np.array([np.fft.irfftn(spec[c], s=shape, axes=(0, 1, 2)) for c in range(3)])
+    del kdotv, inv, K2
+    try:
+        import scipy.fft as sfft
+
+        u = np.array([sfft.irfftn(spec[c], s=shape, axes=(0, 1, 2), workers=os.cpu_count()) for c in range(3)])
+    except ImportError:
+        u = np.array([np.fft.irfftn(spec[c], s=shape, axes=(0, 1, 2)) for c in range(3)])
     scale = rms / math.sqrt(float((u * u).sum(axis=0).mean()) / 3.0)
-    return np.ascontiguousarray(u * scale)
+    u *= scale
+    return np.ascontiguousarray(u)
 
 
 def _shell_vectors(kmax2=4):
