@@ -59,7 +59,7 @@ enum { LBM_CURV_FD = 0, LBM_CURV_MLP = 1 };
 typedef struct lbm_handle lbm_handle;
 
 typedef struct {
-    int32_t nx, ny, nz;  /* each >= 8 */
+    int32_t nx, ny, nz;  /* each >= 8, nx*ny*nz <= 2^30 */
     int32_t storage;     /* LBM_STORE_* */
     int32_t two_phase;   /* 0: single phase (rho = rho_l, no phase field), 1: coupled Allen-Cahn */
     int32_t curv_mode;   /* LBM_CURV_*; LBM_CURV_MLP needs lbm_set_mlp before stepping */

@@ -59,7 +59,7 @@ const char *validate(const lbm_config *c)
     if (!c) return "config is NULL";
     if (c->nx < 8 || c->ny < 8 || c->nz < 8) return "nx, ny, nz must be >= 8";
     const double N = (double)c->nx * c->ny * c->nz;
-    if (N > 2147483647.0) return "nx*ny*nz must be < 2^31";
+    if (N > 1073741824.0) return "nx*ny*nz must be <= 2^30";
     if (c->storage < LBM_STORE_F32 || c->storage > LBM_STORE_BF16) return "storage must be F32, F16 or BF16";
     if (c->two_phase != 0 && c->two_phase != 1) return "two_phase must be 0 or 1";
     if (c->curv_mode != LBM_CURV_FD && c->curv_mode != LBM_CURV_MLP) return "curv_mode must be FD or MLP";
@@ -201,12 +201,14 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
         mt.n = cfg->n_modes;
         for (int m = 0; m < cfg->n_modes; m++) {
             const double *r = cfg->modes + 9 * m;
-            mt.kx[m] = (int)r[0];
-            mt.ky[m] = (int)r[1];
-            mt.kz[m] = (int)r[2];
+            // Re(A e^{i k.x}) = Re(conj(A) e^{-i k.x}): store every row with kz >= 0
+            const double sg = r[2] < 0 ? -1.0 : 1.0;
+            mt.kx[m] = (int)(sg * r[0]);
+            mt.ky[m] = (int)(sg * r[1]);
+            mt.kz[m] = (int)(sg * r[2]);
             for (int a = 0; a < 3; a++) {
                 mt.re[m][a] = (float)r[3 + 2 * a];
-                mt.im[m][a] = (float)r[4 + 2 * a];
+                mt.im[m][a] = (float)(sg * r[4 + 2 * a]);
             }
         }
         lbm::ModeTable *dm = (lbm::ModeTable *)(h->ws + L.modes);

@@ -9,10 +9,16 @@
 //
 // Populations are stored as h_i = f_i / w_i - P0 in FP32, FP16 or BF16; all
 // arithmetic is FP32.  Each phase-field flux through a face or lattice link is
-// evaluated by the same contraction-free code from identical operands on both
-// sides of the link, so the two sites see bit-identical values, and the fluxes
-// are accumulated in FP64 into the FP64 phi: sum phi is conserved to FP64
-// round-off.
+// evaluated by contraction-free code from identical operands on both sides of
+// the link (or once, shared through LDS), so the two sites see bit-identical
+// values; the fluxes are accumulated in FP64 into the FP64 phi, so sum phi is
+// conserved to FP64 round-off.
+//
+// Instruction economy: the D3Q27 weights are a tensor product,
+// w(c) = w1(cx) w1(cy) w1(cz) with w1(0) = 2/3, w1(+-1) = 1/6, so the moments
+// up to second order (of the populations and of the phi stencil) are computed
+// axis by axis, and the post-collision populations, a quadratic polynomial in
+// c, are generated the same way.
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
@@ -53,8 +59,70 @@ template <> struct Pop<2> {
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int modi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
 
-// -------------------------------------------------------- per-site physics
+// element at a 32-bit byte offset from a uniform base: lets the compiler use
+// the scalar-base + 32-bit vector-offset addressing of global memory
+template <class T> __device__ __forceinline__ T ldb(const void *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+template <class T> __device__ __forceinline__ void stb(void *base, uint32_t byte_off, T v)
+{
+    *(T *)((char *)base + byte_off) = v;
+}
+
+// ------------------------------------------------------ separable moments
+// Ten sums M_abc = 216 sum_c w(c) v(c) cx^a cy^b cz^c (a + b + c <= 2) of 27
+// lattice-ordered values, taken axis by axis (x, then y, then z); along each
+// axis the weights are (1, 4, 1) = 6 w1.
+struct M10 {
+    float m000, m100, m010, m001, m200, m020, m002, m110, m101, m011;
+};
+
+__device__ __forceinline__ void moments10(const float (&v)[27], M10 &M)
+{
+    float r0[9], r1[9], r2[9];
+#pragma unroll
+    for (int row = 0; row < 9; row++) {
+        const float vm = v[3 * row], v0 = v[3 * row + 1], vp = v[3 * row + 2];
+        r2[row] = vp + vm;
+        r1[row] = vp - vm;
+        r0[row] = fmaf(4.0f, v0, r2[row]);
+    }
+    float p00[3], p01[3], p02[3], p10[3], p11[3], p20[3];
+#pragma unroll
+    for (int z = 0; z < 3; z++) {
+        const int a = 3 * z, b = 3 * z + 1, c = 3 * z + 2;
+        float s = r0[c] + r0[a];
+        p00[z] = fmaf(4.0f, r0[b], s);
+        p01[z] = r0[c] - r0[a];
+        p02[z] = s;
+        s = r1[c] + r1[a];
+        p10[z] = fmaf(4.0f, r1[b], s);
+        p11[z] = r1[c] - r1[a];
+        p20[z] = fmaf(4.0f, r2[b], r2[c] + r2[a]);
+    }
+    float s = p00[2] + p00[0];
+    M.m000 = fmaf(4.0f, p00[1], s);
+    M.m001 = p00[2] - p00[0];
+    M.m002 = s;
+    s = p01[2] + p01[0];
+    M.m010 = fmaf(4.0f, p01[1], s);
+    M.m011 = p01[2] - p01[0];
+    M.m020 = fmaf(4.0f, p02[1], p02[2] + p02[0]);
+    s = p10[2] + p10[0];
+    M.m100 = fmaf(4.0f, p10[1], s);
+    M.m101 = p10[2] - p10[0];
+    M.m110 = fmaf(4.0f, p11[1], p11[2] + p11[0]);
+    M.m200 = fmaf(4.0f, p20[1], p20[2] + p20[0]);
+}
+
+// ------------------------------------------------------- per-site physics
 struct Macro {
     float dp;     // p* - P0
     float rho;
@@ -63,84 +131,53 @@ struct Macro {
     float S[6];   // Pi - p* c_s^2 I  (xx yy zz xy xz yz)
 };
 
-// Moments of the deviation populations hw_i = f_i - w_i P0 (Sec. 2.2).
-__device__ __forceinline__ void moments(const float (&hw)[27], float &dp, float (&j)[3], float (&S)[6])
+// Phase-field stencil quantities at a site: g = grad phi, H = Hessian (lattice
+// stencils of Sec. 2.3): g = M1 / 72, H_aa = (M_aa - M000/3) / 24, H_ab = M_ab / 24.
+struct PhiGrad {
+    float phi, g[3], H[6];
+};
+
+__device__ __forceinline__ void phi_stencil(const float (&ph)[27], PhiGrad &G)
 {
-    float p = 0.f, jx = 0.f, jy = 0.f, jz = 0.f, xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
-#pragma unroll
-    for (int i = 0; i < 27; i++) {
-        const float v = hw[i];
-        p += v;
-        if (CX(i) > 0) jx += v; else if (CX(i) < 0) jx -= v;
-        if (CY(i) > 0) jy += v; else if (CY(i) < 0) jy -= v;
-        if (CZ(i) > 0) jz += v; else if (CZ(i) < 0) jz -= v;
-        if (CX(i) != 0) xx += v;
-        if (CY(i) != 0) yy += v;
-        if (CZ(i) != 0) zz += v;
-        if (CX(i) * CY(i) > 0) xy += v; else if (CX(i) * CY(i) < 0) xy -= v;
-        if (CX(i) * CZ(i) > 0) xz += v; else if (CX(i) * CZ(i) < 0) xz -= v;
-        if (CY(i) * CZ(i) > 0) yz += v; else if (CY(i) * CZ(i) < 0) yz -= v;
-    }
-    dp = p;
-    j[0] = jx; j[1] = jy; j[2] = jz;
-    const float pc = p * (1.0f / 3.0f);
-    S[0] = xx - pc; S[1] = yy - pc; S[2] = zz - pc;
-    S[3] = xy; S[4] = xz; S[5] = yz;
+    M10 M;
+    moments10(ph, M);
+    const float k1 = 1.0f / 72.0f, k2 = 1.0f / 24.0f, t = M.m000 * (1.0f / 3.0f);
+    G.phi = ph[13];
+    G.g[0] = M.m100 * k1;
+    G.g[1] = M.m010 * k1;
+    G.g[2] = M.m001 * k1;
+    G.H[0] = (M.m200 - t) * k2;
+    G.H[1] = (M.m020 - t) * k2;
+    G.H[2] = (M.m002 - t) * k2;
+    G.H[3] = M.m110 * k2;
+    G.H[4] = M.m101 * k2;
+    G.H[5] = M.m011 * k2;
 }
 
-// Lattice gradient (1/c_s^2) sum w_i psi(x+c_i) c_i and Hessian
-// (1/c_s^4) sum w_i psi(x+c_i) (c_i c_i - c_s^2 I) of a 27-point stencil (Sec. 2.3).
-__device__ __forceinline__ void grad27(const float (&ph)[27], float (&g)[3])
-{
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
-    for (int i = 0; i < 27; i++) {
-        const float v = 3.0f * WT(i) * ph[i];
-        if (CX(i) > 0) gx += v; else if (CX(i) < 0) gx -= v;
-        if (CY(i) > 0) gy += v; else if (CY(i) < 0) gy -= v;
-        if (CZ(i) > 0) gz += v; else if (CZ(i) < 0) gz -= v;
-    }
-    g[0] = gx; g[1] = gy; g[2] = gz;
-}
-
-__device__ __forceinline__ void hess27(const float (&ph)[27], float (&H)[6])
-{
-    // H_aa = 9 sum_{c_a != 0} w psi - 3 sum w psi ; H_ab = 9 sum w psi c_a c_b
-    float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
-#pragma unroll
-    for (int i = 0; i < 27; i++) {
-        const float v = WT(i) * ph[i];
-        s0 += v;
-        if (CX(i) != 0) sx += v;
-        if (CY(i) != 0) sy += v;
-        if (CZ(i) != 0) sz += v;
-        if (CX(i) * CY(i) > 0) xy += v; else if (CX(i) * CY(i) < 0) xy -= v;
-        if (CX(i) * CZ(i) > 0) xz += v; else if (CX(i) * CZ(i) < 0) xz -= v;
-        if (CY(i) * CZ(i) > 0) yz += v; else if (CY(i) * CZ(i) < 0) yz -= v;
-    }
-    H[0] = 9.0f * sx - 3.0f * s0;
-    H[1] = 9.0f * sy - 3.0f * s0;
-    H[2] = 9.0f * sz - 3.0f * s0;
-    H[3] = 9.0f * xy; H[4] = 9.0f * xz; H[5] = 9.0f * yz;
-}
-
-// Forces of Eq. (8) and the velocity u = j + a/2 at one site.
+// Forces of Eq. (8) and the velocity u = j + a/2 from the moments M of the
+// pulled populations h_i = f_i / w_i - P0 (Sec. 2.2).
 //   F^s = -(3 delta/2) sigma K |g| g  with K |g| = tr H - g.H.g / |g|^2
 //   F^p = -p* c_s^2 grad rho,  grad rho = (rho_l - rho_g) g
 //   F^b = rho a_ext
 //   F^nu = -(nu / (tau c_s^2)) (Pi - p* c_s^2 I - u0 u0) grad rho, u0 = j + (F^s + F^p + F^b)/(2 rho)
 template <bool TP>
-__device__ __forceinline__ void site_macro(const float (&hw)[27], const float (&ph)[27], const float (&aext)[3],
-                                           const Params &P, Macro &m)
+__device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const float (&aext)[3], const Params &P,
+                                           Macro &m)
 {
-    float j[3];
-    moments(hw, m.dp, j, m.S);
+    const float r = 1.0f / 216.0f;
+    m.dp = M.m000 * r;
+    float j[3] = {M.m100 * r, M.m010 * r, M.m001 * r};
+    const float pc = m.dp * (1.0f / 3.0f);
+    m.S[0] = fmaf(M.m200, r, -pc);
+    m.S[1] = fmaf(M.m020, r, -pc);
+    m.S[2] = fmaf(M.m002, r, -pc);
+    m.S[3] = M.m110 * r;
+    m.S[4] = M.m101 * r;
+    m.S[5] = M.m011 * r;
     if constexpr (TP) {
-        const float phic = ph[13];
-        const float rho = P.rho_g + (P.rho_l - P.rho_g) * phic;
-        float g[3], H[6];
-        grad27(ph, g);
-        hess27(ph, H);
+        const float rho = P.rho_g + (P.rho_l - P.rho_g) * G.phi;
+        const float *g = G.g;
+        const float *H = G.H;
         const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
         float cs = 0.f;
         if (g2 > 1e-24f) {
@@ -151,8 +188,7 @@ __device__ __forceinline__ void site_macro(const float (&hw)[27], const float (&
             cs = -P.fs_coef * (trH - gHg / g2);
         }
         const float drho = P.rho_l - P.rho_g;
-        const float pstar = P.p0 + m.dp;
-        const float cp = -pstar * (1.0f / 3.0f) * drho;  // F^p = cp * g
+        const float cp = -(P.p0 + m.dp) * (1.0f / 3.0f) * drho;  // F^p = cp * g
         const float inv_rho = 1.0f / rho;
         float F[3], u0[3];
 #pragma unroll
@@ -160,7 +196,6 @@ __device__ __forceinline__ void site_macro(const float (&hw)[27], const float (&
             F[a] = (cs + cp) * g[a] + rho * aext[a];
             u0[a] = j[a] + 0.5f * F[a] * inv_rho;
         }
-        // non-equilibrium stress at u0 contracted with grad rho
         const float n0 = m.S[0] - u0[0] * u0[0], n1 = m.S[1] - u0[1] * u0[1], n2 = m.S[2] - u0[2] * u0[2];
         const float n3 = m.S[3] - u0[0] * u0[1], n4 = m.S[4] - u0[0] * u0[2], n5 = m.S[5] - u0[1] * u0[2];
         const float cnu = -P.fnu_coef * drho;
@@ -183,69 +218,84 @@ __device__ __forceinline__ void site_macro(const float (&hw)[27], const float (&
     }
 }
 
-// Regularised post-collision h_i = f^post_i / w_i - P0 for all 27 directions,
-// f^post = f^eq(p*, u) + (1 - omega) w H : a2 / (2 c_s^4) + S/2 with the
-// closed form a2 = Pi - p* c_s^2 I - u u + (u a + a u)/2.  Each +-c pair shares
-// its even part E and flips its odd part O.
-__device__ __forceinline__ void collide(const Macro &m, float omega, float (&hout)[27])
+// Regularised post-collision h_i = f^post_i / w_i - P0,
+//   f^post = f^eq(p*, u) + (1 - omega) w H : a2 / (2 c_s^4) + S/2,
+//   a2 = Pi - p* c_s^2 I - u u + (u a + a u)/2  (closed form of Eq. (7)),
+// which is the quadratic polynomial h(c) = base + b.c + c.B.c with
+//   b = 3 (u + a/2), B = (9/4)(u w + w u) + (9/2)(1 - omega) a2, w = u + a,
+//   base = p* - P0 - (3/2)(u.u + u.a) - (3/2)(1 - omega) tr a2,
+// evaluated on the 27 velocities axis by axis.
+__device__ __forceinline__ void collide(const Macro &m, float omega, float (&h)[27])
 {
     const float ux = m.u[0], uy = m.u[1], uz = m.u[2];
     const float ax = m.a[0], ay = m.a[1], az = m.a[2];
+    const float wx = ux + ax, wy = uy + ay, wz = uz + az;
     const float k = 4.5f * (1.0f - omega);
-    const float Axx = k * (m.S[0] - ux * ux + ux * ax);
-    const float Ayy = k * (m.S[1] - uy * uy + uy * ay);
-    const float Azz = k * (m.S[2] - uz * uz + uz * az);
-    const float Axy = k * (m.S[3] - ux * uy + 0.5f * (ux * ay + ax * uy));
-    const float Axz = k * (m.S[4] - ux * uz + 0.5f * (ux * az + ax * uz));
-    const float Ayz = k * (m.S[5] - uy * uz + 0.5f * (uy * az + ay * uz));
-    const float u2 = ux * ux + uy * uy + uz * uz;
-    const float ua = ux * ax + uy * ay + uz * az;
-    const float base = m.dp - 1.5f * (u2 + ua) - (Axx + Ayy + Azz) * (1.0f / 3.0f);
-    hout[13] = base;
+    const float Axx = m.S[0] - ux * ux + ux * ax;
+    const float Ayy = m.S[1] - uy * uy + uy * ay;
+    const float Azz = m.S[2] - uz * uz + uz * az;
+    const float Axy = m.S[3] - ux * uy + 0.5f * (ux * ay + ax * uy);
+    const float Axz = m.S[4] - ux * uz + 0.5f * (ux * az + ax * uz);
+    const float Ayz = m.S[5] - uy * uz + 0.5f * (uy * az + ay * uz);
+    const float Bxx = fmaf(k, Axx, 4.5f * ux * wx);
+    const float Byy = fmaf(k, Ayy, 4.5f * uy * wy);
+    const float Bzz = fmaf(k, Azz, 4.5f * uz * wz);
+    const float Bxy2 = 2.0f * fmaf(k, Axy, 2.25f * (ux * wy + wx * uy));
+    const float Bxz2 = 2.0f * fmaf(k, Axz, 2.25f * (ux * wz + wx * uz));
+    const float Byz2 = 2.0f * fmaf(k, Ayz, 2.25f * (uy * wz + wy * uz));
+    const float bx = 3.0f * ux + 1.5f * ax, by = 3.0f * uy + 1.5f * ay, bz = 3.0f * uz + 1.5f * az;
+    const float u2 = ux * ux + uy * uy + uz * uz, ua = ux * ax + uy * ay + uz * az;
+    const float base = m.dp - 1.5f * (u2 + ua) - (k * (1.0f / 3.0f)) * (Axx + Ayy + Azz);
+    const float gz = base + Bzz;
+    const float G[3] = {gz - bz, base, gz + bz};
+    const float Y[3] = {by - Byz2, by, by + Byz2};
+    const float X[3] = {bx - Bxz2, bx, bx + Bxz2};
 #pragma unroll
-    for (int i = 14; i < 27; i++) {
-        const int X = CX(i), Y = CY(i), Z = CZ(i);
-        float cu = 0.f, ca = 0.f, ccA = 0.f;
-        if (X) { cu += X * ux; ca += X * ax; ccA += Axx; }
-        if (Y) { cu += Y * uy; ca += Y * ay; ccA += Ayy; }
-        if (Z) { cu += Z * uz; ca += Z * az; ccA += Azz; }
-        if (X * Y) ccA += 2.0f * X * Y * Axy;
-        if (X * Z) ccA += 2.0f * X * Z * Axz;
-        if (Y * Z) ccA += 2.0f * Y * Z * Ayz;
-        const float E = base + 4.5f * cu * (cu + ca) + ccA;
-        const float O = 3.0f * cu + 1.5f * ca;
-        hout[i] = E + O;
-        hout[26 - i] = E - O;
+    for (int z = 0; z < 3; z++) {
+        const float ty = G[z] + Byy;
+        const float T[3] = {ty - Y[z], G[z], ty + Y[z]};
+        const float Xc[3] = {X[z] - Bxy2, X[z], X[z] + Bxy2};
+#pragma unroll
+        for (int y = 0; y < 3; y++) {
+            const int row = 3 * z + y;
+            const float tx = T[y] + Bxx;
+            h[3 * row] = tx - Xc[y];
+            h[3 * row + 1] = T[y];
+            h[3 * row + 2] = tx + Xc[y];
+        }
     }
 }
 
 // ----------------------------------------------------- phase-field fluxes
 // WENO-5 (Jiang & Shu) value at the face right of cell c from the upwind-biased
-// cells (a, b, c, d, e) = (c-2 .. c+2), linear weights (1/10, 6/10, 3/10),
-// eps = 1e-6; written with one division.  Contraction-free so that both cells
-// of a face compute the same bits.
+// cells (a, b, c, d, e) = (c-2 .. c+2): candidates q_k, smoothness beta_k with
+// the 13/12 and 1/4 factors, linear weights (1/10, 6/10, 3/10), eps = 1e-6,
+// p = 2; the nonlinear weights d_k / (eps + beta_k)^2 are taken with one
+// reciprocal after scaling by the product of the three denominators.
+// Contraction-free (explicit fma only) so both cells of a face get the same bits.
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e)
 {
 #pragma clang fp contract(off)
-    const float q0 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
-    const float q1 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
-    const float q2 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
-    const float t0 = a - 2.0f * b + c, r0 = a - 4.0f * b + 3.0f * c;
-    const float t1 = b - 2.0f * c + d, r1 = b - d;
-    const float t2 = c - 2.0f * d + e, r2 = 3.0f * c - 4.0f * d + e;
-    float s0 = 1e-6f + ((13.0f / 12.0f) * (t0 * t0) + 0.25f * (r0 * r0));
-    float s1 = 1e-6f + ((13.0f / 12.0f) * (t1 * t1) + 0.25f * (r1 * r1));
-    float s2 = 1e-6f + ((13.0f / 12.0f) * (t2 * t2) + 0.25f * (r2 * r2));
+    const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
+    const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
+    const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
+    const float t0 = fmaf(-2.0f, b, a + c), r0 = fmaf(-4.0f, b, fmaf(3.0f, c, a));
+    const float t1 = fmaf(-2.0f, c, b + d), r1 = b - d;
+    const float t2 = fmaf(-2.0f, d, c + e), r2 = fmaf(3.0f, c, fmaf(-4.0f, d, e));
+    float s0 = fmaf((13.0f / 12.0f) * t0, t0, fmaf(0.25f * r0, r0, 1e-6f));
+    float s1 = fmaf((13.0f / 12.0f) * t1, t1, fmaf(0.25f * r1, r1, 1e-6f));
+    float s2 = fmaf((13.0f / 12.0f) * t2, t2, fmaf(0.25f * r2, r2, 1e-6f));
     s0 = s0 * s0;
     s1 = s1 * s1;
     s2 = s2 * s2;
-    // alpha_k = d_k / s_k, scaled by s0 s1 s2
     const float w0 = 0.1f * (s1 * s2), w1 = 0.6f * (s0 * s2), w2 = 0.3f * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    const float num = fmaf(w2, q2, fmaf(w1, q1, w0 * q0));
+    return num * __builtin_amdgcn_rcpf((w0 + w1) + w2);
 }
 
-// Advective flux through the face between cells l and l+1 along one axis:
-// v[k] = phi at l-2+k (k = 0..5), ul / ur = velocity component at l / l+1.
+// Advective flux ubar * phi_face through the face between cells l and l+1:
+// v0..v5 = phi at l-2 .. l+3, ul / ur = velocity component at l / l+1;
+// upwinded by the sign of ubar, zero when ubar == 0.
 __device__ __forceinline__ float face_flux(float v0, float v1, float v2, float v3, float v4, float v5, float ul,
                                            float ur)
 {
@@ -270,63 +320,71 @@ __device__ __forceinline__ float link_flux(float pa, float pb, const float *qa, 
     if constexpr (CY(I) < 0) s = s - (qa[1] + qb[1]);
     if constexpr (CZ(I) > 0) s = s + (qa[2] + qb[2]);
     if constexpr (CZ(I) < 0) s = s - (qa[2] + qb[2]);
-    return d6w * (pa - pb) + k3w * s;
+    return fmaf(k3w, s, d6w * (pa - pb));
 }
 
-// Q = phi (1 - phi) n, n = g / |g| (zero where |g| <= 1e-12), from a 27-point
-// stencil.  Neighbouring workgroups (and the prologue and body of one
-// workgroup) evaluate Q at the same point from different inlined copies of
-// this code, so it is contraction-free: every copy rounds identically.
-__device__ __forceinline__ void q_of(const float (&ph)[27], float (&q)[3])
+// Q = phi (1 - phi) n, n = g / |g| (zero where |g| <= 1e-12), g from the
+// separable first moments (g = M1 / 72; n needs only M1).  Neighbouring
+// workgroups, and the prologue and body of one workgroup, evaluate Q at the
+// same point from different inlined copies: contraction-free, so every copy
+// rounds identically.
+__device__ __forceinline__ void q_of(const float (&v)[27], float (&q)[3])
 {
 #pragma clang fp contract(off)
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+    float d[9], m[9];
 #pragma unroll
-    for (int i = 0; i < 27; i++) {
-        const float v = (3.0f * WT(i)) * ph[i];
-        if (CX(i) > 0) gx = gx + v; else if (CX(i) < 0) gx = gx - v;
-        if (CY(i) > 0) gy = gy + v; else if (CY(i) < 0) gy = gy - v;
-        if (CZ(i) > 0) gz = gz + v; else if (CZ(i) < 0) gz = gz - v;
+    for (int row = 0; row < 9; row++) {
+        d[row] = v[3 * row + 2] - v[3 * row];
+        m[row] = fmaf(4.0f, v[3 * row + 1], v[3 * row + 2] + v[3 * row]);
     }
-    const float g2 = gx * gx + gy * gy + gz * gz;
-    const float c = ph[13] * (1.0f - ph[13]);
-    const float s = g2 > 1e-24f ? c * __frsqrt_rn(g2) : 0.0f;
-    q[0] = s * gx;
-    q[1] = s * gy;
-    q[2] = s * gz;
+    float dx[3], ey[3], sy[3];
+#pragma unroll
+    for (int z = 0; z < 3; z++) {
+        dx[z] = fmaf(4.0f, d[3 * z + 1], d[3 * z + 2] + d[3 * z]);
+        ey[z] = m[3 * z + 2] - m[3 * z];
+        sy[z] = fmaf(4.0f, m[3 * z + 1], m[3 * z + 2] + m[3 * z]);
+    }
+    const float Mx = fmaf(4.0f, dx[1], dx[2] + dx[0]);
+    const float My = fmaf(4.0f, ey[1], ey[2] + ey[0]);
+    const float Mz = sy[2] - sy[0];
+    const float m2 = fmaf(Mx, Mx, fmaf(My, My, Mz * Mz));
+    const float c = v[13] * (1.0f - v[13]);
+    const float s = m2 > 5.184e-21f ? c * __frsqrt_rn(m2) : 0.0f;  // |g| > 1e-12 <=> |M1| > 7.2e-11
+    q[0] = s * Mx;
+    q[1] = s * My;
+    q[2] = s * Mz;
 }
 
 // ----------------------------------------------------------------- forcing
-// Column sums C_k(x, y) = sum_{rows with kz = k} A e^{2 pi i (kx x/nx + ky y/ny)}
-// for k = -2..2; per plane a(x) = sum_k Re(C_k e^{2 pi i k z / nz}).
+// The table holds rows with kz in {0, 1, 2} (the host maps kz < 0 rows to
+// (-k, conj A), which leaves Re(A e^{i theta}) unchanged).  Column sums
+// C_k(x, y) = sum_{rows with kz = k} A e^{2 pi i (kx x/nx + ky y/ny)}; per plane
+// a = Re C_0 + Re(C_1 t) + Re(C_2 t^2), t = e^{2 pi i z / nz}.
 struct Forcing {
-    float cr[5][3], ci[5][3];
+    float c0[3], c1r[3], c1i[3], c2r[3], c2i[3];
 };
 
 __device__ __forceinline__ void forcing_column(const ModeTable *mt, int n, int x, int y, int nx, int ny, Forcing &F)
 {
 #pragma unroll
-    for (int k = 0; k < 5; k++)
-#pragma unroll
-        for (int a = 0; a < 3; a++) F.cr[k][a] = F.ci[k][a] = 0.f;
+    for (int a = 0; a < 3; a++) F.c0[a] = F.c1r[a] = F.c1i[a] = F.c2r[a] = F.c2i[a] = 0.f;
     for (int m = 0; m < n; m++) {
         const int kx = mt->kx[m], ky = mt->ky[m], kz = mt->kz[m];
-        int fx = (kx * x) % nx;
-        if (fx < 0) fx += nx;
-        int fy = (ky * y) % ny;
-        if (fy < 0) fy += ny;
-        const float t = 2.0f * ((float)fx / (float)nx + (float)fy / (float)ny);
+        const int fx = modi(kx * x, nx), fy = modi(ky * y, ny);
         float sn, cs;
-        sincospif(t, &sn, &cs);
+        sincospif(2.0f * ((float)fx / (float)nx + (float)fy / (float)ny), &sn, &cs);
 #pragma unroll
-        for (int k = 0; k < 5; k++) {
-            if (kz == k - 2) {
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    const float ar = mt->re[m][a], ai = mt->im[m][a];
-                    F.cr[k][a] += ar * cs - ai * sn;
-                    F.ci[k][a] += ar * sn + ai * cs;
-                }
+        for (int a = 0; a < 3; a++) {
+            const float ar = mt->re[m][a], ai = mt->im[m][a];
+            const float re = ar * cs - ai * sn, im = ar * sn + ai * cs;
+            if (kz == 0) {
+                F.c0[a] += re;
+            } else if (kz == 1) {
+                F.c1r[a] += re;
+                F.c1i[a] += im;
+            } else {
+                F.c2r[a] += re;
+                F.c2i[a] += im;
             }
         }
     }
@@ -337,31 +395,45 @@ __device__ __forceinline__ void forcing_at(const Forcing &F, int z, int nz, floa
     float s1, c1;
     sincospif(2.0f * (float)z / (float)nz, &s1, &c1);
     const float c2 = c1 * c1 - s1 * s1, s2 = 2.0f * s1 * c1;
-    const float tr[5] = {c2, c1, 1.0f, c1, c2};
-    const float ti[5] = {-s2, -s1, 0.0f, s1, s2};
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-        float v = 0.f;
-#pragma unroll
-        for (int k = 0; k < 5; k++) v += F.cr[k][d] * tr[k] - F.ci[k][d] * ti[k];
-        a[d] = v;
-    }
+    for (int d = 0; d < 3; d++)
+        a[d] = F.c0[d] + (F.c1r[d] * c1 - F.c1i[d] * s1) + (F.c2r[d] * c2 - F.c2i[d] * s2);
 }
 
 // ------------------------------------------------------------ fused step
-constexpr int HX = 3, HY = 3;                 // phi tile halo (WENO-5 needs 3)
+constexpr int HX = 3, HY = 3;                  // phi tile halo (WENO-5 needs 3)
 constexpr int PX = TX + 2 * HX, PY = TY + 2 * HY;
 constexpr int PLANE = PX * PY;                 // phi values per staged plane
 constexpr int QX = TX + 2, QY = TY + 2;        // Q tile (halo 1)
 constexpr int QPLANE = QX * QY;
-constexpr int NRING = 8;                       // phi planes z-3 .. z+4 (power of two)
+constexpr int NRING = 7;                       // phi planes z-3 .. z+3
 constexpr int LOADS = (PLANE + NTHREADS - 1) / NTHREADS;
 constexpr int QPTS = (QPLANE + NTHREADS - 1) / NTHREADS;
+constexpr int NXF = TY * (TX + 1);             // x faces of a plane tile (left of each site + 1)
+constexpr int NYF = (TY + 1) * TX;             // y faces
+constexpr int NFACE = NXF + NYF;
+constexpr int FROUNDS = (NFACE + NTHREADS - 1) / NTHREADS;
 
+__device__ __forceinline__ int ring(int z) { return (z + 4 * NRING) % NRING; }
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations,
+// not for its outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt / expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Software pipeline over the z planes of a chunk: while plane z is processed,
+// the phi plane z+4, the face velocities of plane z+1, the 27 populations of
+// plane z+1 and the site's own phi and u_z ahead are already being fetched.
 template <int S, bool TP, bool FRC>
 __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 {
     using T = typename Pop<S>::T;
+    constexpr uint32_t ES = sizeof(T);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t N = plane * (uint32_t)nz;
@@ -372,6 +444,9 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const T *__restrict__ fin = (const T *)B.fin;
     T *__restrict__ fout = (T *)B.fout;
+    const float *__restrict__ ux_in = B.uin;
+    const float *__restrict__ uy_in = B.uin + N;
+    const float *__restrict__ uz_in = B.uin + 2 * (size_t)N;
 
     // pull sources in the xy plane: index (cy+1)*3 + (cx+1) -> (x - cx, y - cy)
     uint32_t src_xy[9];
@@ -385,41 +460,67 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     Forcing frc;
     if constexpr (FRC) forcing_column(P.modes, P.n_modes, xg, yg, nx, ny, frc);
 
-    // LDS: phi ring (FP32) and Q planes z-1, z, z+1
+    // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
+    float hv[27];
+    auto fetch_pops = [&](int z) {
+        const uint32_t zsrc[3] = {(uint32_t)wrapi(z + 1, nz) * plane, (uint32_t)z * plane,
+                                  (uint32_t)wrapi(z - 1, nz) * plane};
+#pragma unroll
+        for (int i = 0; i < 27; i++) {
+            const uint32_t s = zsrc[CZ(i) + 1] + src_xy[(CY(i) + 1) * 3 + CX(i) + 1];
+            hv[i] = Pop<S>::dec(ldb<T>(fin + (size_t)i * N, s * ES));
+        }
+    };
+
+    // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
+    // the global xy offset of every position of the phi tile
     __shared__ float sphi[TP ? NRING : 1][TP ? PLANE : 1];
     __shared__ float sq[TP ? 3 : 1][3][TP ? QPLANE : 1];
+    __shared__ float sjx[TP ? NXF : 1];
+    __shared__ float sjy[TP ? NYF : 1];
+    __shared__ uint32_t sxy[TP ? PLANE : 1];
     uint32_t ld_xy[LOADS];
     int q_lds[QPTS];
+    int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
+    bool f_isx[FROUNDS];
+    double phn[LOADS];      // prefetched phi plane
+    float f_ul[FROUNDS], f_ur[FROUNDS];  // prefetched face velocities
+    float jz_left = 0.f, uz_c = 0.f, uz_n = 0.f;
+    double po = 0.0;        // prefetched own phi
 
-    if constexpr (TP) {
+    auto fetch_plane = [&](int z) {
+        const double *src = B.phin + (size_t)modi(z, nz) * plane;
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
-            const int ly = e / PX, lx = e - ly * PX;
-            ld_xy[k] = (uint32_t)(((y0 + ly - HY) % ny + ny) % ny) * nx + (uint32_t)(((x0 + lx - HX) % nx + nx) % nx);
+            if (e < PLANE) phn[k] = src[ld_xy[k]];
         }
-#pragma unroll
-        for (int k = 0; k < QPTS; k++) {
-            const int p = tid + k * NTHREADS;
-            const int qy = p / QX, qx = p - qy * QX;
-            q_lds[k] = (qy + 2) * PX + (qx + 2);  // phi tile centre of Q point (qx, qy)
-        }
-    }
-
-    auto load_plane = [&](int z) {
-        const int zw = ((z % nz) + nz) % nz;
-        const double *src = B.phin + (size_t)zw * plane;
-        float *dst = sphi[(z + NRING) & (NRING - 1)];
+    };
+    auto store_plane = [&](int z) {
+        float *dst = sphi[ring(z)];
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
-            if (e < PLANE) dst[e] = (float)src[ld_xy[k]];
+            if (e < PLANE) dst[e] = (float)phn[k];
+        }
+    };
+    auto fetch_face_u = [&](int z) {
+        const uint32_t zo = (uint32_t)z * plane;
+#pragma unroll
+        for (int k = 0; k < FROUNDS; k++) {
+            const int t = tid + k * NTHREADS;
+            if (t < NFACE) {
+                const int c = f_c[k], st = f_isx[k] ? 1 : PX;
+                const float *ub = f_isx[k] ? ux_in : uy_in;
+                f_ul[k] = ub[zo + sxy[c]];
+                f_ur[k] = ub[zo + sxy[c + st]];
+            }
         }
     };
     auto compute_q = [&](int z) {
-        const float *p0 = sphi[(z - 1 + NRING) & (NRING - 1)];
-        const float *p1 = sphi[(z + NRING) & (NRING - 1)];
-        const float *p2 = sphi[(z + 1 + NRING) & (NRING - 1)];
+        const float *p0 = sphi[ring(z - 1)];
+        const float *p1 = sphi[ring(z)];
+        const float *p2 = sphi[ring(z + 1)];
         const int slot = (z + 3) % 3;
 #pragma unroll
         for (int k = 0; k < QPTS; k++) {
@@ -440,139 +541,163 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
             }
         }
     };
+    // advective x and y fluxes of plane z through the faces of the tile, each
+    // face once: x face f of row r lies between tile columns f-1 and f
+    // (f = 0..TX), y face r of column x between tile rows r-1 and r (r = 0..TY)
+    auto compute_faces = [&](int z) {
+        const float *pl = sphi[ring(z)];
+#pragma unroll
+        for (int k = 0; k < FROUNDS; k++) {
+            const int t = tid + k * NTHREADS;
+            if (t < NFACE) {
+                const int c = f_c[k], st = f_isx[k] ? 1 : PX;
+                float *out = f_isx[k] ? sjx + t : sjy + (t - NXF);
+                *out = face_flux(pl[c - 2 * st], pl[c - st], pl[c], pl[c + st], pl[c + 2 * st], pl[c + 3 * st],
+                                 f_ul[k], f_ur[k]);
+            }
+        }
+    };
 
-    float uz_m = 0.f, uz_c = 0.f;  // u_z at (x, y, z-1) and (x, y, z) for the z faces
+    const int lc = (ty + HY) * PX + (tx + HX);  // own phi tile index
+    const int qc = (ty + 1) * QX + (tx + 1);    // own Q tile index
+
     if constexpr (TP) {
-        for (int z = z0 - 3; z <= z0 + 2; z++) load_plane(z);
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < LOADS; k++) {
+            const int e = tid + k * NTHREADS;
+            const int ly = e / PX, lx = e - ly * PX;
+            ld_xy[k] = (uint32_t)modi(y0 + ly - HY, ny) * nx + (uint32_t)modi(x0 + lx - HX, nx);
+            if (e < PLANE) sxy[e] = ld_xy[k];
+        }
+#pragma unroll
+        for (int k = 0; k < QPTS; k++) {
+            const int p = tid + k * NTHREADS;
+            const int qy = p / QX, qx = p - qy * QX;
+            q_lds[k] = (qy + 2) * PX + (qx + 2);  // phi tile centre of Q point (qx, qy)
+        }
+#pragma unroll
+        for (int k = 0; k < FROUNDS; k++) {
+            const int t = tid + k * NTHREADS;
+            if (t < NXF) {
+                const int r = t / (TX + 1), f = t - r * (TX + 1);
+                f_c[k] = (r + HY) * PX + (f - 1 + HX);
+                f_isx[k] = true;
+            } else {
+                const int t2 = t - NXF;
+                const int r = t2 / TX, xx = t2 - r * TX;
+                f_c[k] = (r - 1 + HY) * PX + (xx + HX);
+                f_isx[k] = false;
+            }
+        }
+        for (int z = z0 - 3; z <= z0 + 2; z++) {
+            fetch_plane(z);
+            store_plane(z);
+        }
+        fetch_plane(z0 + 3);
+        lds_barrier();
+        fetch_face_u(z0);
         compute_q(z0 - 1);
         compute_q(z0);
-        const uint32_t zm = (uint32_t)wrapi(z0 - 1, nz);
-        uz_m = B.uin[2 * (size_t)N + zm * plane + own_xy];
-        uz_c = B.uin[2 * (size_t)N + (uint32_t)z0 * plane + own_xy];
+        // z face below the first plane: cells z0-3 .. z0+2, velocities at z0-1, z0
+        const float um = uz_in[(uint32_t)modi(z0 - 1, nz) * plane + own_xy];
+        uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
+        uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
+        po = B.phin[(size_t)z0 * plane + own_xy];
+        float v[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
+        jz_left = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], um, uz_c);
     }
-
-    const int lc = (ty + HY) * PX + (tx + HX);     // own phi tile index
-    const int qc = (ty + 1) * QX + (tx + 1);       // own Q tile index
+    if (active) fetch_pops(z0);
 
     for (int z = z0; z < zend; z++) {
+        const bool more = z + 1 < zend;
         if constexpr (TP) {
-            load_plane(z + 3);
-            __syncthreads();
+            store_plane(z + 3);
+            if (more) fetch_plane(z + 4);
+            lds_barrier();
             compute_q(z + 1);
-            __syncthreads();
+            compute_faces(z);
+            if (more) fetch_face_u(z + 1);
+            lds_barrier();
         }
-        if (!active) continue;
+        if (active) {
+            const uint32_t own = (uint32_t)z * plane + own_xy;
+            M10 M;
+            moments10(hv, M);
+            if (more) fetch_pops(z + 1);
 
-        const uint32_t zc = (uint32_t)z * plane;
-        const uint32_t zsrc[3] = {(uint32_t)wrapi(z + 1, nz) * plane, zc, (uint32_t)wrapi(z - 1, nz) * plane};
-        const uint32_t own = zc + own_xy;
-
-        // 1. pull-stream: f_i(x) = f^post_i(x - c_i)
-        float hw[27];
-#pragma unroll
-        for (int i = 0; i < 27; i++) {
-            const uint32_t s = zsrc[CZ(i) + 1] + src_xy[(CY(i) + 1) * 3 + CX(i) + 1];
-            hw[i] = WT(i) * Pop<S>::dec(fin[(size_t)i * N + s]);
-        }
-
-        // 2. phase-field stencil of this site
-        float ph[27];
-        if constexpr (TP) {
-            const float *pm = sphi[(z - 1 + NRING) & (NRING - 1)];
-            const float *pc = sphi[(z + NRING) & (NRING - 1)];
-            const float *pp = sphi[(z + 1 + NRING) & (NRING - 1)];
-#pragma unroll
-            for (int i = 0; i < 27; i++) {
-                const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
-                ph[i] = pl[lc + CY(i) * PX + CX(i)];
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 27; i++) ph[i] = 0.f;
-        }
-
-        float aext[3] = {0.f, 0.f, 0.f};
-        if constexpr (FRC) forcing_at(frc, z, nz, aext);
-
-        // 3. moments, forces, velocity
-        Macro m;
-        site_macro<TP>(hw, ph, aext, P, m);
-
-        // 4. regularised collision, written to this site's own slots
-        float h[27];
-        collide(m, P.omega, h);
-#pragma unroll
-        for (int i = 0; i < 27; i++) fout[(size_t)i * N + own] = Pop<S>::enc(h[i]);
-
-        if constexpr (TP) {
-            // 5. Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
-            const float *pc = sphi[(z + NRING) & (NRING - 1)];
-            double acc = 0.0;
-            // convective faces; x
-            {
-                const float *r = pc + lc;
-                const float ul = B.uin[zc + (uint32_t)yg * nx + wrapi(xg - 1, nx)];
-                const float uc = B.uin[own];
-                const float ur = B.uin[zc + (uint32_t)yg * nx + wrapi(xg + 1, nx)];
-                const float jr = face_flux(r[-2], r[-1], r[0], r[1], r[2], r[3], uc, ur);
-                const float jl = face_flux(r[-3], r[-2], r[-1], r[0], r[1], r[2], ul, uc);
-                acc += (double)jl - (double)jr;
-            }
-            {  // y
-                const float *r = pc + lc;
-                const float *uy = B.uin + N;
-                const float ul = uy[zc + (uint32_t)wrapi(yg - 1, ny) * nx + xg];
-                const float uc = uy[own];
-                const float ur = uy[zc + (uint32_t)wrapi(yg + 1, ny) * nx + xg];
-                const float jr = face_flux(r[-2 * PX], r[-PX], r[0], r[PX], r[2 * PX], r[3 * PX], uc, ur);
-                const float jl = face_flux(r[-3 * PX], r[-2 * PX], r[-PX], r[0], r[PX], r[2 * PX], ul, uc);
-                acc += (double)jl - (double)jr;
-            }
-            {  // z
-                float v[7];
-#pragma unroll
-                for (int k = 0; k < 7; k++) v[k] = sphi[(z - 3 + k + NRING) & (NRING - 1)][lc];
-                const uint32_t zp = (uint32_t)wrapi(z + 1, nz) * plane;
-                const float up = B.uin[2 * (size_t)N + zp + own_xy];
-                const float jr = face_flux(v[1], v[2], v[3], v[4], v[5], v[6], uz_c, up);
-                const float jl = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], uz_m, uz_c);
-                acc += (double)jl - (double)jr;
-                uz_m = uz_c;
-                uz_c = up;
-            }
-            // diffusion + sharpening through the 13 canonical links, both directions
-            {
-                const float *q0 = sq[(z - 1 + 3) % 3][0];
-                const float *q1 = sq[(z + 3) % 3][0];
-                const float *q2 = sq[(z + 1 + 3) % 3][0];
-                float qs[27][3];
+            PhiGrad G;
+            if constexpr (TP) {
+                // phase-field stencil of this site (LDS)
+                const float *pm = sphi[ring(z - 1)];
+                const float *pc = sphi[ring(z)];
+                const float *pp = sphi[ring(z + 1)];
+                float ph[27];
 #pragma unroll
                 for (int i = 0; i < 27; i++) {
-                    const float *ql = CZ(i) < 0 ? q0 : (CZ(i) > 0 ? q2 : q1);
-                    const int o = qc + CY(i) * QX + CX(i);
-                    qs[i][0] = ql[o];
-                    qs[i][1] = ql[o + QPLANE];
-                    qs[i][2] = ql[o + 2 * QPLANE];
+                    const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
+                    ph[i] = pl[lc + CY(i) * PX + CX(i)];
                 }
-                const float d6w[4] = {0.f, P.d6 * WT(14), P.d6 * WT(15), P.d6 * WT(26)};
-                const float k3w[4] = {0.f, P.k3 * WT(14), P.k3 * WT(15), P.k3 * WT(26)};
-#define LB_LINK(I)                                                                                     \
-    {                                                                                                  \
-        const float fo = link_flux<I>(ph[13], ph[I], qs[13], qs[I], d6w[C2(I)], k3w[C2(I)]);          \
-        const float fi = link_flux<I>(ph[26 - I], ph[13], qs[26 - I], qs[13], d6w[C2(I)], k3w[C2(I)]); \
-        acc += (double)fi - (double)fo;                                                                \
+                phi_stencil(ph, G);
+
+                // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
+                double acc = 0.0;
+                acc += (double)sjx[ty * (TX + 1) + tx] - (double)sjx[ty * (TX + 1) + tx + 1];
+                acc += (double)sjy[ty * TX + tx] - (double)sjy[(ty + 1) * TX + tx];
+                {
+                    float v[6];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) v[k] = sphi[ring(z - 2 + k)][lc];
+                    const float jr = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], uz_c, uz_n);
+                    acc += (double)jz_left - (double)jr;
+                    jz_left = jr;
+                    uz_c = uz_n;
+                    if (more) uz_n = uz_in[(uint32_t)wrapi(z + 2, nz) * plane + own_xy];
+                }
+                {
+                    const float *q0 = sq[(z - 1 + 3) % 3][0];
+                    const float *q1 = sq[(z + 3) % 3][0];
+                    const float *q2 = sq[(z + 1 + 3) % 3][0];
+                    const float qo[3] = {q1[qc], q1[qc + QPLANE], q1[qc + 2 * QPLANE]};
+                    const float d6w[4] = {0.f, P.d6 * WT(14), P.d6 * WT(15), P.d6 * WT(26)};
+                    const float k3w[4] = {0.f, P.k3 * WT(14), P.k3 * WT(15), P.k3 * WT(26)};
+#define LB_LINK(I)                                                                                    \
+    {                                                                                                 \
+        const float *qp = (CZ(I) > 0 ? q2 : q1) + qc + CY(I) * QX + CX(I);                            \
+        const float *qm = (CZ(I) > 0 ? q0 : q1) + qc - CY(I) * QX - CX(I);                            \
+        const float qn[3] = {qp[0], qp[QPLANE], qp[2 * QPLANE]};                                      \
+        const float qs[3] = {qm[0], qm[QPLANE], qm[2 * QPLANE]};                                      \
+        const float fo = link_flux<I>(ph[13], ph[I], qo, qn, d6w[C2(I)], k3w[C2(I)]);                 \
+        const float fi = link_flux<I>(ph[26 - I], ph[13], qs, qo, d6w[C2(I)], k3w[C2(I)]);            \
+        acc += (double)fi - (double)fo;                                                               \
     }
-                LB_LINK(14) LB_LINK(15) LB_LINK(16) LB_LINK(17) LB_LINK(18) LB_LINK(19) LB_LINK(20)
-                LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
+                    LB_LINK(14) LB_LINK(15) LB_LINK(16) LB_LINK(17) LB_LINK(18) LB_LINK(19) LB_LINK(20)
+                    LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
+                }
+                B.phout[(size_t)own] = po + acc;
+                if (more) po = B.phin[(size_t)own + plane];
             }
-            B.phout[own] = B.phin[own] + acc;
-        }
-        if constexpr (TP) {  // velocity of this step, advects phi in the next one
-            B.uout[own] = m.u[0];
-            B.uout[(size_t)N + own] = m.u[1];
-            B.uout[2 * (size_t)N + own] = m.u[2];
+
+            float aext[3] = {0.f, 0.f, 0.f};
+            if constexpr (FRC) forcing_at(frc, z, nz, aext);
+
+            // moments -> forces, velocity
+            Macro m;
+            site_macro<TP>(M, G, aext, P, m);
+
+            // regularised collision, written to this site's own slots
+            float h[27];
+            collide(m, P.omega, h);
+#pragma unroll
+            for (int i = 0; i < 27; i++) stb<T>(fout + (size_t)i * N, own * ES, Pop<S>::enc(h[i]));
+
+            if constexpr (TP) {  // velocity of this step, advects phi in the next one
+                stb<float>(B.uout, own * 4u, m.u[0]);
+                stb<float>(B.uout + N, own * 4u, m.u[1]);
+                stb<float>(B.uout + 2 * (size_t)N, own * 4u, m.u[2]);
+            }
         }
     }
 }
@@ -633,7 +758,7 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double
 // Per-site macroscopic state at time n (pull + stencils from global memory).
 template <int S, bool TP, bool FRC>
 __device__ __forceinline__ void site_state(const Params &P, const void *fin_, const double *phi, uint32_t s,
-                                           Macro &m, float &phic)
+                                           Macro &m)
 {
     using T = typename Pop<S>::T;
     const T *fin = (const T *)fin_;
@@ -643,15 +768,15 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     auto nb = [&](int dx, int dy, int dz) {
         return (uint32_t)wrapi(z + dz, nz) * plane + (uint32_t)wrapi(y + dy, ny) * nx + (uint32_t)wrapi(x + dx, nx);
     };
-    float hw[27], ph[27];
+    float hv[27];
 #pragma unroll
-    for (int i = 0; i < 27; i++) hw[i] = WT(i) * Pop<S>::dec(fin[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))]);
+    for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))]);
+    PhiGrad G;
     if constexpr (TP) {
+        float ph[27];
 #pragma unroll
         for (int i = 0; i < 27; i++) ph[i] = (float)phi[nb(CX(i), CY(i), CZ(i))];
-    } else {
-#pragma unroll
-        for (int i = 0; i < 27; i++) ph[i] = 0.f;
+        phi_stencil(ph, G);
     }
     float aext[3] = {0.f, 0.f, 0.f};
     if constexpr (FRC) {
@@ -659,8 +784,9 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
         forcing_column(P.modes, P.n_modes, x, y, nx, ny, F);
         forcing_at(F, z, nz, aext);
     }
-    site_macro<TP>(hw, ph, aext, P, m);
-    phic = TP ? (float)phi[s] : 0.f;
+    M10 M;
+    moments10(hv, M);
+    site_macro<TP>(M, G, aext, P, m);
 }
 
 template <int S, bool TP, bool FRC>
@@ -671,8 +797,7 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin,
     const uint32_t s = blockIdx.x * NTHREADS + threadIdx.x;
     if (s >= N) return;
     Macro m;
-    float phic;
-    site_state<S, TP, FRC>(P, fin, phi, s, m, phic);
+    site_state<S, TP, FRC>(P, fin, phi, s, m);
     if (rho) rho[s] = m.rho;
     if (pr) pr[s] = (P.p0 + m.dp) * m.rho * (1.0f / 3.0f);
     if (u) {
@@ -694,8 +819,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, 
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
     for (uint32_t s = blockIdx.x * NTHREADS + threadIdx.x; s < N; s += gridDim.x * NTHREADS) {
         Macro m;
-        float phic_f;
-        site_state<S, TP, FRC>(P, fin, phi, s, m, phic_f);
+        site_state<S, TP, FRC>(P, fin, phi, s, m);
         const double ph = TP ? phi[s] : 0.0;
         const double r = m.rho, pstar = (double)P.p0 + (double)m.dp;
         const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
