@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 10 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -134,6 +136,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_mib": args.copy_mib, "copy_gbs": 2 * a.numel() / dt / 1e9}), flush=True)
+        return
     t_setup = time.perf_counter()
     shape, phi0, u0, params, nb = workload(args.size)
     print(f"# inputs ready in {time.perf_counter() - t_setup:.1f} s: {args.size}^3, {nb} bubbles", file=sys.stderr,

@@ -127,6 +127,52 @@ int lbm_set_stream(lbm_handle *h, void *stream);
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int lbm_destroy(lbm_handle *h);
 
+/* ------------------------------------------------------------------ learned curvature
+ * A small network maps the 3^3 phi stencil of an interface cell to its
+ * curvature and normal (an extension of the finite-difference curvature of
+ * Sec. 2.3, used where bubbles are under-resolved): inputs x = 2 phi - 1 on
+ * the 27 lattice directions (fp16, rows padded to LBM_MLP_IN = 32 with zeros),
+ * two tanh hidden layers of 64, outputs (K, n_x, n_y, n_z).  Parameters are
+ * LBM_MLP_NPARAM IEEE binary16 values (uint16_t bits) in the order
+ * W1[64][27], b1[64], W2[64][64], b2[64], W3[4][64], b3[4].  Matrix products run
+ * on FP16 MFMA with FP32 accumulation; hidden activations are rounded to fp16. */
+#define LBM_MLP_IN 32
+#define LBM_MLP_MAX_SPHERES 1024
+
+/* Device bytes of scratch lbm_mlp_backward needs for a batch of B samples. */
+size_t lbm_mlp_work_bytes(int64_t batch);
+
+/* y[B][4] (FP32) = network(x[B][32]) for B >= 0 samples; asynchronous on stream. */
+int lbm_mlp_forward(const uint16_t *d_w, const uint16_t *d_x, int64_t batch, float *d_y, void *stream);
+
+/* Gradient of the loss (1/B) sum_b sum_k (y_bk - t_bk)^2 with respect to the
+ * parameters, written as FP32 [LBM_MLP_NPARAM] to d_grad (same order as the
+ * weights), and the loss to d_loss[0] (FP32).  d_work: lbm_mlp_work_bytes(B)
+ * bytes of device scratch.  Deterministic (fixed reduction order). */
+int lbm_mlp_backward(const uint16_t *d_w, const uint16_t *d_x, const float *d_t, int64_t batch, float *d_grad,
+                     float *d_loss, void *d_work, size_t work_bytes, void *stream);
+
+/* One Adam step on FP32 master weights (Kingma & Ba): m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, w -= lr mhat / (sqrt(vhat) + eps) with bias correction
+ * at step >= 1; the fp16 copy d_w16 is refreshed (round to nearest even). */
+int lbm_mlp_adam(float *d_master, float *d_m, float *d_v, const float *d_grad, uint16_t *d_w16, int64_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Install network weights (device fp16 array) into the handle; required before
+ * lbm_step when curv_mode is LBM_CURV_MLP.  Asynchronous on the handle's stream. */
+int lbm_set_mlp(lbm_handle *h, const uint16_t *d_w);
+
+/* Training samples from the handle's current phi: every interface cell
+ * (0.02 < phi < 0.98), in site order, gives the input row 2 phi - 1 on its 3^3
+ * stencil and the label of the nearest sphere (by | |x - c| - |R| |, periodic):
+ * K = -2/R for a phi = 1 sphere (R > 0), +2/R for a phi = 0 sphere (R < 0),
+ * normal = radial unit vector toward phi = 1.  centers [nb][3] (x, y, z) and
+ * radii [nb] are HOST arrays, nb <= LBM_MLP_MAX_SPHERES.  At most cap rows are
+ * written to d_x [cap][32] (fp16) and d_y [cap][4] (FP32); *n_out (host) gets
+ * the total count.  Waits for the stream. */
+int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int nb, uint16_t *d_x, float *d_y,
+                int64_t cap, int64_t *n_out);
+
 /* Static text for an error code. */
 const char *lbm_strerror(int code);
 

@@ -575,6 +575,22 @@ double orc_mlp_loss_grad(const double *w, const double *x, const double *yt, lon
     return loss / (double)B;
 }
 
+/* Adam (Kingma & Ba 2015) on FP64 master weights with bias correction at
+ * step t >= 1; w16 receives the fp16 rounding of the updated weights. */
+void orc_adam(double *w, double *m, double *v, const double *g, long n, long t, double lr, double b1, double b2,
+              double eps, double *w16)
+{
+    double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (long p = 0; p < n; p++) {
+        m[p] = b1 * m[p] + (1.0 - b1) * g[p];
+        v[p] = b2 * v[p] + (1.0 - b2) * g[p] * g[p];
+        double mhat = m[p] / c1, vhat = v[p] / c2;
+        w[p] -= lr * mhat / (sqrt(vhat) + eps);
+        if (w16)
+            w16[p] = orc_to_half(w[p]);
+    }
+}
+
 /* curvature and normal used by the surface-tension force: finite differences,
  * or the smooth blend with the network output where |K_FD| exceeds k_lo */
 static void site_curvature(const orc_state *s, long st, const long nb[Q], const double g[3], double *K,

@@ -81,6 +81,8 @@ double orc_to_half(double v);          /* IEEE binary16 round-to-nearest-even, a
 void orc_mlp_set_fp16(int on);         /* 0 disables the fp16 emulation (gradient checks) */
 void orc_mlp_forward(const double *w, const double *x /* B*27 */, long B, double *y /* B*4 */);
 double orc_mlp_loss_grad(const double *w, const double *x, const double *yt, long B, double *grad /* NPARAM */);
+void orc_adam(double *w, double *m, double *v, const double *g, long n, long t, double lr, double b1, double b2,
+              double eps, double *w16);
 void orc_harvest(int nx, int ny, int nz, const double *phi, const double *centers, const double *radii, int nb,
                  double *X /* cap*27 */, double *Y /* cap*4 */, long cap, long *n_out);
 

@@ -65,6 +65,8 @@ def lib():
         L.orc_mlp_forward.argtypes = [dp, dp, C.c_long, dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_long, dp]
+        L.orc_adam.argtypes = [dp, dp, dp, dp, C.c_long, C.c_long, C.c_double, C.c_double, C.c_double,
+                               C.c_double, dp]
         L.orc_harvest.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, dp, C.c_long,
                                   C.POINTER(C.c_long)]
         _lib = L
@@ -175,6 +177,16 @@ def mlp_loss_grad(w, x, yt):
     g = np.zeros(MLP_NPARAM)
     loss = lib().orc_mlp_loss_grad(_p(w), _p(x), _p(yt), x.shape[0], _p(g))
     return loss, g
+
+
+def adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays; returns the fp16-rounded weights."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    w16 = np.zeros_like(w)
+    lib().orc_adam(_p(w), _p(m), _p(v), _p(g), len(w), int(t), lr, b1, b2, eps, _p(w16))
+    return w16
 
 
 def harvest(phi, centers, radii, cap=1 << 20):

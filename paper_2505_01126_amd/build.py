@@ -6,7 +6,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_mlp.hip", "lbm_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -8,6 +8,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "lbm.h"
 #include "lbm_internal.h"
@@ -23,7 +25,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], modes, partials, red, mlp, total;
+    size_t f[2], phi[2], u[2], fcol, fz, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -46,10 +48,17 @@ Layout layout_of(const lbm_config &c)
     } else {
         L.phi[0] = L.phi[1] = L.u[0] = L.u[1] = (size_t)-1;
     }
-    L.modes = take(sizeof(lbm::ModeTable));
+    if (c.n_modes > 0) {
+        L.fcol = take(sizeof(float) * lbm::FCOL * (size_t)c.nx * c.ny);
+        L.fz = take(sizeof(float) * 4 * (size_t)c.nz);
+    } else {
+        L.fcol = L.fz = (size_t)-1;
+    }
     L.partials = take(sizeof(double) * lbm::RED_BLOCKS * lbm::NRED);
     L.red = take(sizeof(double) * lbm::NRED);
     L.mlp = take(sizeof(uint16_t) * LBM_MLP_NPARAM);
+    L.sph = take(sizeof(double) * 4 * lbm::MAX_SPHERES);
+    L.hcount = take(sizeof(long long) * 2 * lbm::HARVEST_BLOCKS);
     L.total = off;
     return L;
 }
@@ -106,7 +115,7 @@ struct lbm_handle {
     int cur = 0;
     int64_t steps = 0;
     bool mlp_set = false;
-    lbm::ModeTable modes_host{};
+    std::vector<float> fcol_host, fz_host;
     std::string err;
 
     void *f(int k) { return ws + L.f[k]; }
@@ -194,32 +203,74 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
     P.k_lo = (float)lo;
     P.k_hi = (float)hi;
     P.mlp = h->ws + L.mlp;
-    P.modes = nullptr;
+    P.fcol = nullptr;
+    P.fz = nullptr;
+    P.gx = (cfg->nx + lbm::TX - 1) / lbm::TX;
+    P.gy = (cfg->ny + lbm::TY - 1) / lbm::TY;
+    P.gz = (cfg->nz + P.zchunk - 1) / P.zchunk;
+    P.nblocks = P.gx * P.gy * P.gz;
 
     if (cfg->n_modes > 0) {
-        lbm::ModeTable &mt = h->modes_host;
-        mt.n = cfg->n_modes;
-        for (int m = 0; m < cfg->n_modes; m++) {
-            const double *r = cfg->modes + 9 * m;
-            // Re(A e^{i k.x}) = Re(conj(A) e^{-i k.x}): store every row with kz >= 0
-            const double sg = r[2] < 0 ? -1.0 : 1.0;
-            mt.kx[m] = (int)(sg * r[0]);
-            mt.ky[m] = (int)(sg * r[1]);
-            mt.kz[m] = (int)(sg * r[2]);
-            for (int a = 0; a < 3; a++) {
-                mt.re[m][a] = (float)r[3 + 2 * a];
-                mt.im[m][a] = (float)(sg * r[4 + 2 * a]);
+        // body-force tables in FP64 on the host, stored as FP32
+        const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+        const size_t plane = (size_t)nx * ny;
+        h->fcol_host.assign((size_t)lbm::FCOL * plane, 0.0f);
+        h->fz_host.assign((size_t)4 * nz, 0.0f);
+        std::vector<double> acc(lbm::FCOL);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                std::fill(acc.begin(), acc.end(), 0.0);
+                for (int m = 0; m < cfg->n_modes; m++) {
+                    const double *r = cfg->modes + 9 * m;
+                    // Re(A e^{i k.x}) = Re(conj(A) e^{-i k.x}): use kz >= 0
+                    const double sg = r[2] < 0 ? -1.0 : 1.0;
+                    const long kx = (long)(sg * r[0]), ky = (long)(sg * r[1]), kz = (long)(sg * r[2]);
+                    const long fx = ((kx * x) % nx + nx) % nx, fy = ((ky * y) % ny + ny) % ny;
+                    const double th = two_pi * ((double)fx / nx + (double)fy / ny);
+                    const double cs = std::cos(th), sn = std::sin(th);
+                    for (int a = 0; a < 3; a++) {
+                        const double ar = r[3 + 2 * a], ai = sg * r[4 + 2 * a];
+                        const double re = ar * cs - ai * sn, im = ar * sn + ai * cs;
+                        if (kz == 0) {
+                            acc[a] += re;
+                        } else if (kz == 1) {
+                            acc[3 + a] += re;
+                            acc[6 + a] += im;
+                        } else {
+                            acc[9 + a] += re;
+                            acc[12 + a] += im;
+                        }
+                    }
+                }
+                for (int k = 0; k < lbm::FCOL; k++) h->fcol_host[(size_t)k * plane + (size_t)y * nx + x] = (float)acc[k];
             }
+        for (int z = 0; z < nz; z++) {
+            const double t = two_pi * (double)z / nz;
+            h->fz_host[4 * z + 0] = (float)std::cos(t);
+            h->fz_host[4 * z + 1] = (float)std::sin(t);
+            h->fz_host[4 * z + 2] = (float)std::cos(2.0 * t);
+            h->fz_host[4 * z + 3] = (float)std::sin(2.0 * t);
         }
-        lbm::ModeTable *dm = (lbm::ModeTable *)(h->ws + L.modes);
-        hipError_t e = hipMemcpyAsync(dm, &mt, sizeof(mt), hipMemcpyHostToDevice, h->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging must outlive the copy
+        float *dcol = (float *)(h->ws + L.fcol);
+        float4 *dz = (float4 *)(h->ws + L.fz);
+        hipError_t e = hipMemcpyAsync(dcol, h->fcol_host.data(), sizeof(float) * h->fcol_host.size(),
+                                      hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dz, h->fz_host.data(), sizeof(float) * h->fz_host.size(), hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging is released below
+        h->fcol_host.clear();
+        h->fcol_host.shrink_to_fit();
+        h->fz_host.clear();
+        h->fz_host.shrink_to_fit();
         if (e != hipSuccess) {
-            g_init_err = std::string("mode table upload: ") + hipGetErrorString(e);
+            g_init_err = std::string("forcing table upload: ") + hipGetErrorString(e);
             delete h;
             return LBM_EHIP;
         }
-        P.modes = dm;
+        P.fcol = dcol;
+        P.fz = dz;
     }
     hipError_t e = lbm::launch_init(P, cfg->storage, h->f(0), h->phi(0), h->u(0), d_phi0, d_u0, d_pstar0, h->stream);
     if (e != hipSuccess) {
@@ -273,6 +324,95 @@ int lbm_reduce(lbm_handle *h, double *out, int out_is_host)
 }
 
 int64_t lbm_steps_done(const lbm_handle *h) { return h ? h->steps : -1; }
+
+size_t lbm_mlp_work_bytes(int64_t batch)
+{
+    if (batch < 0) return 0;
+    return sizeof(float) * (size_t)lbm::mlp_backward_blocks(batch) * (LBM_MLP_NPARAM + 1);
+}
+
+int lbm_mlp_forward(const uint16_t *d_w, const uint16_t *d_x, int64_t batch, float *d_y, void *stream)
+{
+    if (!d_w || batch < 0 || (batch > 0 && (!d_x || !d_y))) return LBM_EINVAL;
+    return lbm::launch_mlp_forward(d_w, d_x, batch, d_y, (hipStream_t)stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+int lbm_mlp_backward(const uint16_t *d_w, const uint16_t *d_x, const float *d_t, int64_t batch, float *d_grad,
+                     float *d_loss, void *d_work, size_t work_bytes, void *stream)
+{
+    if (!d_w || batch < 0 || !d_grad || !d_loss || !d_work || (batch > 0 && (!d_x || !d_t))) return LBM_EINVAL;
+    if (work_bytes < lbm_mlp_work_bytes(batch)) return LBM_ENOSPACE;
+    return lbm::launch_mlp_backward(d_w, d_x, d_t, batch, d_grad, d_loss, (float *)d_work, (hipStream_t)stream) ==
+                   hipSuccess
+               ? LBM_OK
+               : LBM_EHIP;
+}
+
+int lbm_mlp_adam(float *d_master, float *d_m, float *d_v, const float *d_grad, uint16_t *d_w16, int64_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!d_master || !d_m || !d_v || !d_grad || !d_w16 || step < 1) return LBM_EINVAL;
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f)) return LBM_EINVAL;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+    return lbm::launch_mlp_adam(d_master, d_m, d_v, d_grad, d_w16, lr, beta1, beta2, eps, c1, c2,
+                                (hipStream_t)stream) == hipSuccess
+               ? LBM_OK
+               : LBM_EHIP;
+}
+
+int lbm_set_mlp(lbm_handle *h, const uint16_t *d_w)
+{
+    if (!h || !d_w) return LBM_EINVAL;
+    hipError_t e = hipMemcpyAsync(h->ws + h->L.mlp, d_w, sizeof(uint16_t) * LBM_MLP_NPARAM, hipMemcpyDeviceToDevice,
+                                  h->stream);
+    if (e != hipSuccess) return h->hip(e, "set_mlp copy");
+    h->mlp_set = true;
+    return LBM_OK;
+}
+
+int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int nb, uint16_t *d_x, float *d_y,
+                int64_t cap, int64_t *n_out)
+{
+    if (!h || !n_out || cap < 0 || nb < 0 || nb > LBM_MLP_MAX_SPHERES || (nb > 0 && (!centers || !radii)) ||
+        (cap > 0 && (!d_x || !d_y)))
+        return LBM_EINVAL;
+    if (!h->cfg.two_phase) return h->fail(LBM_ESTATE, "harvest needs a two-phase handle");
+    const uint32_t N = (uint32_t)h->cfg.nx * h->cfg.ny * h->cfg.nz;
+    const int blocks = (int)std::min<uint32_t>((N + 255) / 256, lbm::HARVEST_BLOCKS);
+    const uint32_t chunk = ((N + blocks - 1) / blocks + 255) / 256 * 256;
+    std::vector<double> sph(4 * (size_t)std::max(nb, 1), 0.0);
+    for (int k = 0; k < nb; k++) {
+        sph[4 * k + 0] = centers[3 * k + 0];
+        sph[4 * k + 1] = centers[3 * k + 1];
+        sph[4 * k + 2] = centers[3 * k + 2];
+        sph[4 * k + 3] = radii[k];
+    }
+    long long *counts = (long long *)(h->ws + h->L.hcount);
+    long long *offsets = counts + lbm::HARVEST_BLOCKS;
+    std::vector<long long> hc(blocks), ho(blocks);
+    const double *phi = h->phi(h->cur);
+    hipError_t e = hipMemcpyAsync(h->ws + h->L.sph, sph.data(), sizeof(double) * 4 * nb, hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = lbm::launch_harvest_count(phi, N, chunk, blocks, counts, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hc.data(), counts, sizeof(long long) * blocks, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip(e, "harvest count");
+    long long total = 0;
+    for (int b = 0; b < blocks; b++) {
+        ho[b] = total;
+        total += hc[b];
+    }
+    e = hipMemcpyAsync(offsets, ho.data(), sizeof(long long) * blocks, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && cap > 0)
+        e = lbm::launch_harvest_write(h->P, phi, chunk, blocks, offsets, h->ws + h->L.sph, nb, d_x, d_y, cap,
+                                      h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip(e, "harvest write");
+    *n_out = total;
+    return LBM_OK;
+}
 
 int lbm_set_stream(lbm_handle *h, void *stream)
 {

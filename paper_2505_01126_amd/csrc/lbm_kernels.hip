@@ -356,48 +356,26 @@ __device__ __forceinline__ void q_of(const float (&v)[27], float (&q)[3])
 }
 
 // ----------------------------------------------------------------- forcing
-// The table holds rows with kz in {0, 1, 2} (the host maps kz < 0 rows to
-// (-k, conj A), which leaves Re(A e^{i theta}) unchanged).  Column sums
-// C_k(x, y) = sum_{rows with kz = k} A e^{2 pi i (kx x/nx + ky y/ny)}; per plane
-// a = Re C_0 + Re(C_1 t) + Re(C_2 t^2), t = e^{2 pi i z / nz}.
+// Time-independent body acceleration (Sec. 5.1 uses a fixed large-scale
+// field).  The host tabulates, per (x, y) column, the sums C_k over the mode
+// rows with kz = k (see lbm_internal.h); per plane a = Re C0 + Re(C1 t) + Re(C2 t^2).
 struct Forcing {
-    float c0[3], c1r[3], c1i[3], c2r[3], c2i[3];
+    float c[FCOL];
 };
 
-__device__ __forceinline__ void forcing_column(const ModeTable *mt, int n, int x, int y, int nx, int ny, Forcing &F)
+__device__ __forceinline__ void forcing_column(const Params &P, uint32_t xy, Forcing &F)
 {
+    const uint32_t plane = (uint32_t)P.nx * P.ny;
 #pragma unroll
-    for (int a = 0; a < 3; a++) F.c0[a] = F.c1r[a] = F.c1i[a] = F.c2r[a] = F.c2i[a] = 0.f;
-    for (int m = 0; m < n; m++) {
-        const int kx = mt->kx[m], ky = mt->ky[m], kz = mt->kz[m];
-        const int fx = modi(kx * x, nx), fy = modi(ky * y, ny);
-        float sn, cs;
-        sincospif(2.0f * ((float)fx / (float)nx + (float)fy / (float)ny), &sn, &cs);
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const float ar = mt->re[m][a], ai = mt->im[m][a];
-            const float re = ar * cs - ai * sn, im = ar * sn + ai * cs;
-            if (kz == 0) {
-                F.c0[a] += re;
-            } else if (kz == 1) {
-                F.c1r[a] += re;
-                F.c1i[a] += im;
-            } else {
-                F.c2r[a] += re;
-                F.c2i[a] += im;
-            }
-        }
-    }
+    for (int k = 0; k < FCOL; k++) F.c[k] = P.fcol[k * plane + xy];
 }
 
-__device__ __forceinline__ void forcing_at(const Forcing &F, int z, int nz, float (&a)[3])
+__device__ __forceinline__ void forcing_at(const Forcing &F, const Params &P, int z, float (&a)[3])
 {
-    float s1, c1;
-    sincospif(2.0f * (float)z / (float)nz, &s1, &c1);
-    const float c2 = c1 * c1 - s1 * s1, s2 = 2.0f * s1 * c1;
+    const float4 t = P.fz[z];  // cos 2pi z/nz, sin, cos 4pi z/nz, sin
 #pragma unroll
     for (int d = 0; d < 3; d++)
-        a[d] = F.c0[d] + (F.c1r[d] * c1 - F.c1i[d] * s1) + (F.c2r[d] * c2 - F.c2i[d] * s2);
+        a[d] = F.c[d] + (F.c[3 + d] * t.x - F.c[6 + d] * t.y) + (F.c[9 + d] * t.z - F.c[12 + d] * t.w);
 }
 
 // ------------------------------------------------------------ fused step
@@ -438,7 +416,15 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t N = plane * (uint32_t)nz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * P.zchunk;
+    // Workgroups are handed to the 8 XCDs round-robin by launch index; give
+    // XCD j a contiguous run of tiles (x fastest, then y, then z chunk) so that
+    // neighbouring tiles share that XCD's L2 (halo rows, +-1 shifted rows).
+    const uint32_t H = blockIdx.x, q8 = (uint32_t)P.nblocks / 8u, r8 = (uint32_t)P.nblocks % 8u;
+    const uint32_t xcd = H % 8u, idx = H / 8u;
+    const uint32_t L = (xcd < r8 ? xcd * (q8 + 1u) : r8 * (q8 + 1u) + (xcd - r8) * q8) + idx;
+    const int bx = (int)(L % (uint32_t)P.gx), by = (int)((L / (uint32_t)P.gx) % (uint32_t)P.gy);
+    const int bz = (int)(L / ((uint32_t)P.gx * (uint32_t)P.gy));
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * P.zchunk;
     const int zend = min(z0 + P.zchunk, nz);
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
@@ -458,7 +444,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     const uint32_t own_xy = (uint32_t)yg * nx + xg;
 
     Forcing frc;
-    if constexpr (FRC) forcing_column(P.modes, P.n_modes, xg, yg, nx, ny, frc);
+    if constexpr (FRC) forcing_column(P, own_xy, frc);
 
     // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
     float hv[27];
@@ -629,18 +615,6 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 
             PhiGrad G;
             if constexpr (TP) {
-                // phase-field stencil of this site (LDS)
-                const float *pm = sphi[ring(z - 1)];
-                const float *pc = sphi[ring(z)];
-                const float *pp = sphi[ring(z + 1)];
-                float ph[27];
-#pragma unroll
-                for (int i = 0; i < 27; i++) {
-                    const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
-                    ph[i] = pl[lc + CY(i) * PX + CX(i)];
-                }
-                phi_stencil(ph, G);
-
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
                 double acc = 0.0;
                 acc += (double)sjx[ty * (TX + 1) + tx] - (double)sjx[ty * (TX + 1) + tx + 1];
@@ -656,6 +630,17 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                     if (more) uz_n = uz_in[(uint32_t)wrapi(z + 2, nz) * plane + own_xy];
                 }
                 {
+                    // phase-field stencil of this site (LDS)
+                    const float *pm = sphi[ring(z - 1)];
+                    const float *pc = sphi[ring(z)];
+                    const float *pp = sphi[ring(z + 1)];
+                    float ph[27];
+#pragma unroll
+                    for (int i = 0; i < 27; i++) {
+                        const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
+                        ph[i] = pl[lc + CY(i) * PX + CX(i)];
+                    }
+                    phi_stencil(ph, G);
                     const float *q0 = sq[(z - 1 + 3) % 3][0];
                     const float *q1 = sq[(z + 3) % 3][0];
                     const float *q2 = sq[(z + 1 + 3) % 3][0];
@@ -681,7 +666,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
             }
 
             float aext[3] = {0.f, 0.f, 0.f};
-            if constexpr (FRC) forcing_at(frc, z, nz, aext);
+            if constexpr (FRC) forcing_at(frc, P, z, aext);
 
             // moments -> forces, velocity
             Macro m;
@@ -781,8 +766,8 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     float aext[3] = {0.f, 0.f, 0.f};
     if constexpr (FRC) {
         Forcing F;
-        forcing_column(P.modes, P.n_modes, x, y, nx, ny, F);
-        forcing_at(F, z, nz, aext);
+        forcing_column(P, (uint32_t)y * nx + x, F);
+        forcing_at(F, P, z, aext);
     }
     M10 M;
     moments10(hv, M);
@@ -901,8 +886,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
 
 hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream_t s)
 {
-    dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, (p.nz + p.zchunk - 1) / p.zchunk);
-    dim3 block(TX, TY, 1);
+    dim3 grid(p.nblocks), block(TX, TY, 1);
     const bool tp = p.two_phase != 0, frc = p.n_modes > 0;
 #define CALL(S_, TP_, F_) hipLaunchKernelGGL((k_step<S_, TP_, F_>), grid, block, 0, s, p, b);
     LBM_DISPATCH(storage, tp, frc, CALL);

@@ -54,7 +54,17 @@ SYMBOLS = {
     "lbm_destroy": (C.c_int, [C.c_void_p]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_mlp_work_bytes": (C.c_size_t, [C.c_int64]),
+    "lbm_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "lbm_mlp_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lbm_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                               C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "lbm_set_mlp": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_harvest": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_void_p,
+                              C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
 }
+MLP_IN = 32
 
 
 def load_library(path=LIBPATH):
@@ -131,6 +141,39 @@ def lbm_set_stream(h, stream):
 
 def lbm_destroy(h):
     load_library().lbm_destroy(h)
+
+
+def lbm_mlp_work_bytes(batch):
+    return load_library().lbm_mlp_work_bytes(int(batch))
+
+
+def lbm_mlp_forward(d_w, d_x, batch, d_y, stream):
+    _check(load_library().lbm_mlp_forward(d_w, d_x, int(batch), d_y, stream), None, "lbm_mlp_forward")
+
+
+def lbm_mlp_backward(d_w, d_x, d_t, batch, d_grad, d_loss, d_work, work_bytes, stream):
+    _check(load_library().lbm_mlp_backward(d_w, d_x, d_t, int(batch), d_grad, d_loss, d_work, work_bytes, stream),
+           None, "lbm_mlp_backward")
+
+
+def lbm_mlp_adam(d_master, d_m, d_v, d_grad, d_w16, step, lr, beta1, beta2, eps, stream):
+    _check(load_library().lbm_mlp_adam(d_master, d_m, d_v, d_grad, d_w16, int(step), lr, beta1, beta2, eps, stream),
+           None, "lbm_mlp_adam")
+
+
+def lbm_set_mlp(h, d_w):
+    _check(load_library().lbm_set_mlp(h, d_w), h, "lbm_set_mlp")
+
+
+def lbm_harvest(h, centers, radii, d_x, d_y, cap):
+    """centers [nb,3], radii [nb] host float64; returns the total count."""
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    n = C.c_int64(0)
+    dp = C.POINTER(C.c_double)
+    _check(load_library().lbm_harvest(h, c.ctypes.data_as(dp), r.ctypes.data_as(dp), len(r), d_x, d_y, int(cap),
+                                      C.byref(n)), h, "lbm_harvest")
+    return n.value
 
 
 def _torch():
@@ -225,3 +268,63 @@ class Lattice:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def set_mlp(self, w16):
+        """Install fp16 network weights (torch.int16/uint16-compatible device tensor of 6212 values)."""
+        self._mlp_w = w16.contiguous()
+        lbm_set_mlp(self.h, _ptr(self._mlp_w))
+
+    def harvest(self, centers, radii, cap):
+        """Training rows from the current phi: (X [n,32] fp16 bits as int16, Y [n,4] fp32, total count)."""
+        torch = self.torch
+        X = torch.zeros((max(cap, 1), MLP_IN), dtype=torch.int16, device=self.device)
+        Y = torch.zeros((max(cap, 1), 4), dtype=torch.float32, device=self.device)
+        n = lbm_harvest(self.h, centers, radii, _ptr(X), _ptr(Y), cap)
+        m = min(n, cap)
+        return X[:m], Y[:m], n
+
+
+class Mlp:
+    """Device-side network parameters plus Adam state; every computation runs in
+    the library's MFMA kernels."""
+
+    def __init__(self, w_init, device="cuda:0"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        w = np.asarray(w_init, dtype=np.float64).reshape(-1)
+        if w.size != MLP_NPARAM:
+            raise LbmError(f"expected {MLP_NPARAM} parameters")
+        self.master = torch.tensor(w.astype(np.float32), device=self.device)
+        self.w16 = torch.tensor(w.astype(np.float16).view(np.int16), device=self.device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.t = 0
+        self._work = None
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, X):
+        y = self.torch.empty((X.shape[0], 4), dtype=self.torch.float32, device=self.device)
+        lbm_mlp_forward(_ptr(self.w16), _ptr(X), X.shape[0], _ptr(y), self.stream())
+        return y
+
+    def backward(self, X, T):
+        B = X.shape[0]
+        need = lbm_mlp_work_bytes(B)
+        if self._work is None or self._work.numel() < need:
+            self._work = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        lbm_mlp_backward(_ptr(self.w16), _ptr(X), _ptr(T), B, _ptr(self.grad), _ptr(self.loss), _ptr(self._work),
+                         self._work.numel(), self.stream())
+        return self.grad, self.loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        lbm_mlp_adam(_ptr(self.master), _ptr(self.m), _ptr(self.v), _ptr(self.grad), _ptr(self.w16), self.t, lr,
+                     beta1, beta2, eps, self.stream())
+
+    def weights_fp16(self):
+        return self.w16.cpu().numpy().view(np.float16).astype(np.float64)

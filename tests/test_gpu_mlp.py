@@ -1,0 +1,141 @@
+"""Learned-curvature network kernels (FP16 MFMA) against the FP64 oracle.
+
+The oracle evaluates the same network with fp16 rounding of the inputs and of
+the hidden activations; the GPU accumulates in FP32 inside the MFMA, so an
+activation can land on the other side of an fp16 rounding boundary (one fp16
+ulp, ~5e-4 relative).  Bars: forward outputs within 2e-3 of the output scale,
+gradient relative L2 error below 1e-2 (the GPU backward runs its products on
+fp16 operands), loss within 1e-3.  Batch sizes are ragged against the 16-sample
+MFMA tile and the 64-sample workgroup chunk.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_01126_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+NP = O.MLP_NPARAM
+
+
+def _lbm():
+    from paper_2505_01126_amd import lbm
+
+    return lbm
+
+
+def _weights(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(NP) * scale
+    return w.astype(np.float16).astype(np.float64)
+
+
+def _inputs(B, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, (B, 27)).astype(np.float16).astype(np.float64)
+    xp = np.zeros((B, 32), dtype=np.float16)
+    xp[:, :27] = x
+    return x, xp
+
+
+def _dev_x(xp):
+    import torch
+
+    return torch.tensor(xp.view(np.int16), device="cuda")
+
+
+@pytest.mark.parametrize("B", [1, 37, 1000])
+def test_forward_matches_oracle(B):
+    import torch
+
+    lbm = _lbm()
+    w = _weights(1)
+    x, xp = _inputs(B, 2)
+    net = lbm.Mlp(w)
+    y = net.forward(_dev_x(xp)).cpu().numpy().astype(np.float64)
+    yo = O.mlp_forward(w, x)
+    scale = np.abs(yo).max()
+    err = np.abs(y - yo)
+    print(f"forward B={B}: max err {err.max():.3e}, median {np.median(err):.3e}, scale {scale:.3f}")
+    assert err.max() < 2e-3 * scale
+    assert np.median(err) < 1e-4 * scale
+
+
+@pytest.mark.parametrize("B", [50, 777])
+def test_backward_matches_oracle(B):
+    import torch
+
+    lbm = _lbm()
+    w = _weights(3)
+    x, xp = _inputs(B, 4)
+    t = np.random.default_rng(5).uniform(-1, 1, (B, 4))
+    net = lbm.Mlp(w)
+    g, loss = net.backward(_dev_x(xp), torch.tensor(t, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy().astype(np.float64)
+    loss = float(loss.cpu().numpy()[0])
+    lo, go = O.mlp_loss_grad(w, x, t.astype(np.float32).astype(np.float64))
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"backward B={B}: grad rel err {rel:.3e}, loss {loss:.6f} vs {lo:.6f}")
+    assert rel < 1e-2
+    assert loss == pytest.approx(lo, rel=1e-3)
+    # every parameter block gets a gradient
+    for a, b in ((0, 1728), (1728, 1792), (1792, 5888), (5888, 5952), (5952, 6208), (6208, 6212)):
+        assert np.linalg.norm(g[a:b] - go[a:b]) <= 2e-2 * np.linalg.norm(go[a:b]) + 1e-7
+
+
+def test_backward_deterministic_and_empty_batch():
+    import torch
+
+    lbm = _lbm()
+    w = _weights(6)
+    x, xp = _inputs(300, 7)
+    t = torch.tensor(np.random.default_rng(8).uniform(-1, 1, (300, 4)), dtype=torch.float32, device="cuda")
+    net = lbm.Mlp(w)
+    g1 = net.backward(_dev_x(xp), t)[0].clone()
+    g2 = net.backward(_dev_x(xp), t)[0].clone()
+    assert torch.equal(g1, g2)
+    y = net.forward(_dev_x(xp[:0]))
+    assert y.shape == (0, 4)
+
+
+def test_adam_matches_oracle():
+    import torch
+
+    lbm = _lbm()
+    w = _weights(9)
+    x, xp = _inputs(200, 10)
+    t = np.random.default_rng(11).uniform(-1, 1, (200, 4))
+    net = lbm.Mlp(w)
+    wo = net.master.cpu().numpy().astype(np.float64)
+    mo = np.zeros(NP)
+    vo = np.zeros(NP)
+    for step in range(1, 4):
+        g, _ = net.backward(_dev_x(xp), torch.tensor(t, dtype=torch.float32, device="cuda"))
+        gh = g.cpu().numpy().astype(np.float64)
+        net.adam(lr=1e-3)
+        w16o = O.adam(wo, mo, vo, gh, step, lr=1e-3)
+    wm = net.master.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(wm, wo, rtol=1e-5, atol=1e-6)
+    w16 = net.weights_fp16()
+    assert np.mean(w16 == w16o) > 0.999
+
+
+def test_harvest_matches_oracle():
+    lbm = _lbm()
+    shape = (24, 28, 70)
+    phi0, c, r = I.bubble_pack(shape, 3, (6.0, 10.0), seed=12)
+    drop, cd = I.droplet(shape, 5.0, 4.0, center=(50.3, 8.2, 12.7))
+    phi = np.minimum(phi0, 1.0 - drop) * 0 + phi0  # bubbles only
+    g = lbm.Lattice(shape, 0.8, phi0=phi, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    radii = -r  # phi = 0 inside
+    X, Y, n = g.harvest(c, radii, cap=1 << 16)
+    Xo, Yo, no = O.harvest(phi, c, radii)
+    assert n == no == len(Xo)
+    x16 = X.cpu().numpy().view(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(x16[:, :27], Xo.astype(np.float16).astype(np.float64))
+    assert (x16[:, 27:] == 0).all()
+    np.testing.assert_allclose(Y.cpu().numpy(), Yo, rtol=1e-6, atol=1e-7)
+    # capacity smaller than the count: first rows only, total still reported
+    X2, Y2, n2 = g.harvest(c, radii, cap=100)
+    assert n2 == n and len(X2) == 100
+    np.testing.assert_array_equal(X2.cpu().numpy(), X[:100].cpu().numpy())

@@ -103,3 +103,20 @@ def test_harvest_labels_on_sphere():
     Xb, Yb, cb = O.harvest(1 - phi, np.array([c]), np.array([-R]))
     np.testing.assert_allclose(Yb[:, 0], 2.0 / R)
     np.testing.assert_allclose(Yb[:, 1:], -Y[:, 1:], atol=1e-14)
+
+
+def test_adam_first_steps_closed_form():
+    """With a constant gradient g the bias-corrected Adam step is
+    lr * g / (|g| + eps) at every step (mhat = g, vhat = g^2)."""
+    n = 7
+    g = np.array([1e-3, -2.0, 0.5, 3e-5, -7.0, 1.0, 0.0])
+    w = np.linspace(-1, 1, n)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    w0 = w.copy()
+    lr, eps = 1e-2, 1e-8
+    for t in (1, 2, 3):
+        w16 = O.adam(w, m, v, g, t, lr=lr, eps=eps)
+        step = lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(w, w0 - t * step, rtol=1e-12, atol=1e-15)
+        np.testing.assert_array_equal(w16, w.astype(np.float16).astype(np.float64))
