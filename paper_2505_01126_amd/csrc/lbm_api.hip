@@ -301,6 +301,7 @@ int lbm_step(lbm_handle *h, int64_t nsteps)
 int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_phi)
 {
     if (!h) return LBM_EINVAL;
+    if (h->cfg.curv_mode == LBM_CURV_MLP && !h->mlp_set) return h->fail(LBM_ESTATE, "MLP weights not set");
     const int c = h->cur;
     hipError_t e = lbm::launch_moments(h->P, h->cfg.storage, h->f(c), h->phi(c), d_rho, d_p, d_u, d_phi, h->stream);
     return h->hip(e, "moments kernel");
@@ -309,6 +310,7 @@ int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_p
 int lbm_reduce(lbm_handle *h, double *out, int out_is_host)
 {
     if (!h || !out) return LBM_EINVAL;
+    if (h->cfg.curv_mode == LBM_CURV_MLP && !h->mlp_set) return h->fail(LBM_ESTATE, "MLP weights not set");
     const int c = h->cur;
     double *red = (double *)(h->ws + h->L.red);
     hipError_t e = lbm::launch_reduce(h->P, h->cfg.storage, h->f(c), h->phi(c), (double *)(h->ws + h->L.partials),

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
+#include "lbm_mlp_device.h"
 
 namespace lbm {
 
@@ -154,15 +155,79 @@ __device__ __forceinline__ void phi_stencil(const float (&ph)[27], PhiGrad &G)
     G.H[5] = M.m011 * k2;
 }
 
+// Surface-tension force with the finite-difference curvature (Sec. 2.3 CSF
+// form): F^s = -(3 delta/2) sigma K |g| g, with K |g| = tr H - g.H.g / |g|^2
+// (K = div n, n = g/|g| toward phi = 1); zero where |g| <= 1e-12.
+__device__ __forceinline__ void surface_fd(const PhiGrad &G, const Params &P, float (&fs)[3])
+{
+    const float *g = G.g, *H = G.H;
+    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    float cs = 0.f;
+    if (g2 > 1e-24f) {
+        const float trH = H[0] + H[1] + H[2];
+        const float gHg = g[0] * (H[0] * g[0] + H[3] * g[1] + H[4] * g[2]) +
+                          g[1] * (H[3] * g[0] + H[1] * g[1] + H[5] * g[2]) +
+                          g[2] * (H[4] * g[0] + H[5] * g[1] + H[2] * g[2]);
+        cs = -P.fs_coef * (trH - gHg / g2);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) fs[a] = cs * g[a];
+}
+
+// Learned curvature: K_FD and |g| at the site, and whether the network is
+// consulted (interface cell 0.02 < phi < 0.98 with |K_FD| > k_lo).
+__device__ __forceinline__ bool mlp_select(const PhiGrad &G, const Params &P, float &kfd, float &gn)
+{
+    const float *g = G.g, *H = G.H;
+    const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    kfd = 0.f;
+    gn = 0.f;
+    if (!(g2 > 1e-24f)) return false;
+    const float trH = H[0] + H[1] + H[2];
+    const float gHg = g[0] * (H[0] * g[0] + H[3] * g[1] + H[4] * g[2]) +
+                      g[1] * (H[3] * g[0] + H[1] * g[1] + H[5] * g[2]) +
+                      g[2] * (H[4] * g[0] + H[5] * g[1] + H[2] * g[2]);
+    gn = sqrtf(g2);
+    kfd = (trH - gHg / g2) / gn;
+    return G.phi > 0.02f && G.phi < 0.98f && fabsf(kfd) > P.k_lo;
+}
+
+// Blend of the network output y = (K, n) with the finite-difference K and n:
+// s = smoothstep((|K_FD| - k_lo) / (k_hi - k_lo)), K = s K_net + (1 - s) K_FD,
+// n_s = normalise(s n_net/|n_net| + (1 - s) g/|g|), F^s = -(3 delta/2) sigma K |g|^2 n_s;
+// the finite-difference force is kept when the output is non-finite or
+// |n_net| is outside [0.5, 1.5].
+__device__ __forceinline__ void surface_blend(const PhiGrad &G, const Params &P, float kfd, float gn,
+                                              const float (&y)[4], float (&fs)[3])
+{
+    const float nn = sqrtf(y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+    if (!(isfinite(y[0]) && isfinite(nn) && nn >= 0.5f && nn <= 1.5f)) {
+        surface_fd(G, P, fs);
+        return;
+    }
+    const float t = fminf((fabsf(kfd) - P.k_lo) / (P.k_hi - P.k_lo), 1.0f);
+    const float sw = t * t * (3.0f - 2.0f * t);
+    const float K = sw * y[0] + (1.0f - sw) * kfd;
+    float b[3], bn2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        b[a] = sw * y[1 + a] / nn + (1.0f - sw) * G.g[a] / gn;
+        bn2 += b[a] * b[a];
+    }
+    const float bn = sqrtf(bn2);
+    const float c = -P.fs_coef * K * gn * gn;
+#pragma unroll
+    for (int a = 0; a < 3; a++) fs[a] = c * (bn > 1e-12f ? b[a] / bn : G.g[a] / gn);
+}
+
 // Forces of Eq. (8) and the velocity u = j + a/2 from the moments M of the
-// pulled populations h_i = f_i / w_i - P0 (Sec. 2.2).
-//   F^s = -(3 delta/2) sigma K |g| g  with K |g| = tr H - g.H.g / |g|^2
+// pulled populations h_i = f_i / w_i - P0 (Sec. 2.2); fs is the surface-tension force.
 //   F^p = -p* c_s^2 grad rho,  grad rho = (rho_l - rho_g) g
 //   F^b = rho a_ext
 //   F^nu = -(nu / (tau c_s^2)) (Pi - p* c_s^2 I - u0 u0) grad rho, u0 = j + (F^s + F^p + F^b)/(2 rho)
 template <bool TP>
-__device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const float (&aext)[3], const Params &P,
-                                           Macro &m)
+__device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const float (&fs)[3],
+                                           const float (&aext)[3], const Params &P, Macro &m)
 {
     const float r = 1.0f / 216.0f;
     m.dp = M.m000 * r;
@@ -177,23 +242,13 @@ __device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const
     if constexpr (TP) {
         const float rho = P.rho_g + (P.rho_l - P.rho_g) * G.phi;
         const float *g = G.g;
-        const float *H = G.H;
-        const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-        float cs = 0.f;
-        if (g2 > 1e-24f) {
-            const float trH = H[0] + H[1] + H[2];
-            const float gHg = g[0] * (H[0] * g[0] + H[3] * g[1] + H[4] * g[2]) +
-                              g[1] * (H[3] * g[0] + H[1] * g[1] + H[5] * g[2]) +
-                              g[2] * (H[4] * g[0] + H[5] * g[1] + H[2] * g[2]);
-            cs = -P.fs_coef * (trH - gHg / g2);
-        }
         const float drho = P.rho_l - P.rho_g;
         const float cp = -(P.p0 + m.dp) * (1.0f / 3.0f) * drho;  // F^p = cp * g
         const float inv_rho = 1.0f / rho;
         float F[3], u0[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            F[a] = (cs + cp) * g[a] + rho * aext[a];
+            F[a] = fs[a] + cp * g[a] + rho * aext[a];
             u0[a] = j[a] + 0.5f * F[a] * inv_rho;
         }
         const float n0 = m.S[0] - u0[0] * u0[0], n1 = m.S[1] - u0[1] * u0[1], n2 = m.S[2] - u0[2] * u0[2];
@@ -407,7 +462,7 @@ __device__ __forceinline__ void lds_barrier()
 // Software pipeline over the z planes of a chunk: while plane z is processed,
 // the phi plane z+4, the face velocities of plane z+1, the 27 populations of
 // plane z+1 and the site's own phi and u_z ahead are already being fetched.
-template <int S, bool TP, bool FRC>
+template <int S, bool TP, bool FRC, bool ML>
 __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 {
     using T = typename Pop<S>::T;
@@ -465,6 +520,11 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     __shared__ float sjx[TP ? NXF : 1];
     __shared__ float sjy[TP ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
+    // learned curvature: weights and per-wave scratch
+    __shared__ char mlp_raw[ML ? sizeof(MlpW) + TY * sizeof(MlpWave) : 1];
+    MlpW &smw = *(MlpW *)mlp_raw;
+    MlpWave *smwave = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
+    if constexpr (ML) load_weights((const uint16_t *)P.mlp, smw, tid, NTHREADS);
     uint32_t ld_xy[LOADS];
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
@@ -607,13 +667,16 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
             if (more) fetch_face_u(z + 1);
             lds_barrier();
         }
+        const uint32_t own = (uint32_t)z * plane + own_xy;
+        M10 M;
+        PhiGrad G;
+        float ph[27];
+        float kfd = 0.f, gn = 0.f;
+        bool sel = false;
         if (active) {
-            const uint32_t own = (uint32_t)z * plane + own_xy;
-            M10 M;
             moments10(hv, M);
             if (more) fetch_pops(z + 1);
 
-            PhiGrad G;
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
                 double acc = 0.0;
@@ -634,13 +697,13 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                     const float *pm = sphi[ring(z - 1)];
                     const float *pc = sphi[ring(z)];
                     const float *pp = sphi[ring(z + 1)];
-                    float ph[27];
 #pragma unroll
                     for (int i = 0; i < 27; i++) {
                         const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
                         ph[i] = pl[lc + CY(i) * PX + CX(i)];
                     }
                     phi_stencil(ph, G);
+                    if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
                     const float *q0 = sq[(z - 1 + 3) % 3][0];
                     const float *q1 = sq[(z + 3) % 3][0];
                     const float *q2 = sq[(z + 1 + 3) % 3][0];
@@ -664,13 +727,27 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                 B.phout[(size_t)own] = po + acc;
                 if (more) po = B.phin[(size_t)own + plane];
             }
-
+        }
+        // surface tension: finite differences, or blended with the network
+        // evaluated on the wave's selected interface cells (all lanes together)
+        float fs[3] = {0.f, 0.f, 0.f};
+        if constexpr (ML) {
+            float y[4] = {0.f, 0.f, 0.f, 0.f};
+            mlp_wave(smw, smwave[ty], sel, ph, y, tx);
+            if (active) {
+                if (sel) surface_blend(G, P, kfd, gn, y, fs);
+                else surface_fd(G, P, fs);
+            }
+        } else if constexpr (TP) {
+            if (active) surface_fd(G, P, fs);
+        }
+        if (active) {
             float aext[3] = {0.f, 0.f, 0.f};
             if constexpr (FRC) forcing_at(frc, P, z, aext);
 
             // moments -> forces, velocity
             Macro m;
-            site_macro<TP>(M, G, aext, P, m);
+            site_macro<TP>(M, G, fs, aext, P, m);
 
             // regularised collision, written to this site's own slots
             float h[27];
@@ -741,9 +818,11 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double
 
 // -------------------------------------------------- fields and reductions
 // Per-site macroscopic state at time n (pull + stencils from global memory).
-template <int S, bool TP, bool FRC>
+// Every lane of the wave calls this together (the network stage is a
+// wave-wide MFMA); lanes with valid == false only take part in that stage.
+template <int S, bool TP, bool FRC, bool ML>
 __device__ __forceinline__ void site_state(const Params &P, const void *fin_, const double *phi, uint32_t s,
-                                           Macro &m)
+                                           bool valid, Macro &m, const MlpW &W, MlpWave &wv, int lane)
 {
     using T = typename Pop<S>::T;
     const T *fin = (const T *)fin_;
@@ -753,36 +832,62 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     auto nb = [&](int dx, int dy, int dz) {
         return (uint32_t)wrapi(z + dz, nz) * plane + (uint32_t)wrapi(y + dy, ny) * nx + (uint32_t)wrapi(x + dx, nx);
     };
-    float hv[27];
-#pragma unroll
-    for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))]);
-    PhiGrad G;
-    if constexpr (TP) {
-        float ph[27];
-#pragma unroll
-        for (int i = 0; i < 27; i++) ph[i] = (float)phi[nb(CX(i), CY(i), CZ(i))];
-        phi_stencil(ph, G);
-    }
-    float aext[3] = {0.f, 0.f, 0.f};
-    if constexpr (FRC) {
-        Forcing F;
-        forcing_column(P, (uint32_t)y * nx + x, F);
-        forcing_at(F, P, z, aext);
-    }
     M10 M;
-    moments10(hv, M);
-    site_macro<TP>(M, G, aext, P, m);
+    PhiGrad G;
+    float ph[27];
+    float kfd = 0.f, gn = 0.f;
+    bool sel = false;
+    if (valid) {
+        float hv[27];
+#pragma unroll
+        for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))]);
+        moments10(hv, M);
+        if constexpr (TP) {
+#pragma unroll
+            for (int i = 0; i < 27; i++) ph[i] = (float)phi[nb(CX(i), CY(i), CZ(i))];
+            phi_stencil(ph, G);
+            if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
+        }
+    }
+    float fs[3] = {0.f, 0.f, 0.f};
+    if constexpr (ML) {
+        float yv[4] = {0.f, 0.f, 0.f, 0.f};
+        mlp_wave(W, wv, sel, ph, yv, lane);
+        if (valid) {
+            if (sel) surface_blend(G, P, kfd, gn, yv, fs);
+            else surface_fd(G, P, fs);
+        }
+    } else if constexpr (TP) {
+        if (valid) surface_fd(G, P, fs);
+    }
+    if (valid) {
+        float aext[3] = {0.f, 0.f, 0.f};
+        if constexpr (FRC) {
+            Forcing F;
+            forcing_column(P, (uint32_t)y * nx + x, F);
+            forcing_at(F, P, z, aext);
+        }
+        site_macro<TP>(M, G, fs, aext, P, m);
+    }
 }
 
-template <int S, bool TP, bool FRC>
+template <int S, bool TP, bool FRC, bool ML>
 __global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin, const double *phi, float *rho,
                                                       float *pr, float *u, double *phi_out)
 {
+    __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
+    MlpW &W = *(MlpW *)mlp_raw;
+    MlpWave *wv = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
+    if constexpr (ML) {
+        load_weights((const uint16_t *)P.mlp, W, threadIdx.x, NTHREADS);
+        __syncthreads();
+    }
     const uint32_t N = (uint32_t)P.nx * P.ny * P.nz;
     const uint32_t s = blockIdx.x * NTHREADS + threadIdx.x;
-    if (s >= N) return;
+    const bool valid = s < N;
     Macro m;
-    site_state<S, TP, FRC>(P, fin, phi, s, m);
+    site_state<S, TP, FRC, ML>(P, fin, phi, valid ? s : 0u, valid, m, W, wv[threadIdx.x >> 6], threadIdx.x & 63);
+    if (!valid) return;
     if (rho) rho[s] = m.rho;
     if (pr) pr[s] = (P.p0 + m.dp) * m.rho * (1.0f / 3.0f);
     if (u) {
@@ -795,16 +900,28 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin,
 
 // FP64 partial sums per block over a fixed grid-stride partition, combined in
 // a fixed order: the result does not depend on scheduling.
-template <int S, bool TP, bool FRC>
+template <int S, bool TP, bool FRC, bool ML>
 __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, const double *phi, double *partials)
 {
+    __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
+    MlpW &W = *(MlpW *)mlp_raw;
+    MlpWave *wv = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
+    if constexpr (ML) {
+        load_weights((const uint16_t *)P.mlp, W, threadIdx.x, NTHREADS);
+        __syncthreads();
+    }
     const uint32_t N = (uint32_t)P.nx * P.ny * P.nz;
     double acc[NRED];
 #pragma unroll
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
-    for (uint32_t s = blockIdx.x * NTHREADS + threadIdx.x; s < N; s += gridDim.x * NTHREADS) {
+    // uniform trip count across the block (the network stage is wave-wide)
+    for (uint32_t base = blockIdx.x * NTHREADS; base < N; base += gridDim.x * NTHREADS) {
+        const uint32_t s = base + threadIdx.x;
+        const bool valid = s < N;
         Macro m;
-        site_state<S, TP, FRC>(P, fin, phi, s, m);
+        site_state<S, TP, FRC, ML>(P, fin, phi, valid ? s : 0u, valid, m, W, wv[threadIdx.x >> 6],
+                                   threadIdx.x & 63);
+        if (!valid) continue;
         const double ph = TP ? phi[s] : 0.0;
         const double r = m.rho, pstar = (double)P.p0 + (double)m.dp;
         const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
@@ -870,26 +987,30 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
 }
 
 // --------------------------------------------------------------- launchers
-#define LBM_DISPATCH(storage, tp, frc, CALL)                      \
-    do {                                                          \
-        if (storage == 0) {                                       \
-            if (tp) { if (frc) CALL(0, true, true) else CALL(0, true, false) }   \
-            else { if (frc) CALL(0, false, true) else CALL(0, false, false) }    \
-        } else if (storage == 1) {                                \
-            if (tp) { if (frc) CALL(1, true, true) else CALL(1, true, false) }   \
-            else { if (frc) CALL(1, false, true) else CALL(1, false, false) }    \
-        } else {                                                  \
-            if (tp) { if (frc) CALL(2, true, true) else CALL(2, true, false) }   \
-            else { if (frc) CALL(2, false, true) else CALL(2, false, false) }    \
-        }                                                         \
+// template dispatch: storage x two-phase x forcing x learned curvature
+// (the learned curvature exists only with the phase field)
+#define LBM_DISPATCH_S(S_, tp, frc, ml, CALL)                                  \
+    do {                                                                       \
+        if (tp) {                                                              \
+            if (ml) { if (frc) CALL(S_, true, true, true) else CALL(S_, true, false, true) } \
+            else { if (frc) CALL(S_, true, true, false) else CALL(S_, true, false, false) }  \
+        } else {                                                               \
+            if (frc) CALL(S_, false, true, false) else CALL(S_, false, false, false)        \
+        }                                                                      \
+    } while (0)
+#define LBM_DISPATCH(storage, tp, frc, ml, CALL)                               \
+    do {                                                                       \
+        if (storage == 0) LBM_DISPATCH_S(0, tp, frc, ml, CALL);                \
+        else if (storage == 1) LBM_DISPATCH_S(1, tp, frc, ml, CALL);           \
+        else LBM_DISPATCH_S(2, tp, frc, ml, CALL);                             \
     } while (0)
 
 hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream_t s)
 {
     dim3 grid(p.nblocks), block(TX, TY, 1);
-    const bool tp = p.two_phase != 0, frc = p.n_modes > 0;
-#define CALL(S_, TP_, F_) hipLaunchKernelGGL((k_step<S_, TP_, F_>), grid, block, 0, s, p, b);
-    LBM_DISPATCH(storage, tp, frc, CALL);
+    const bool tp = p.two_phase != 0, frc = p.n_modes > 0, ml = p.curv_mode == 1;
+#define CALL(S_, TP_, F_, M_) hipLaunchKernelGGL((k_step<S_, TP_, F_, M_>), grid, block, 0, s, p, b);
+    LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     return hipGetLastError();
 }
@@ -910,10 +1031,10 @@ hipError_t launch_moments(const Params &p, int storage, const void *fin, const d
 {
     const uint32_t N = (uint32_t)p.nx * p.ny * p.nz;
     dim3 grid((N + NTHREADS - 1) / NTHREADS), block(NTHREADS);
-    const bool tp = p.two_phase != 0, frc = p.n_modes > 0;
-#define CALL(S_, TP_, F_) \
-    hipLaunchKernelGGL((k_moments<S_, TP_, F_>), grid, block, 0, s, p, fin, phi, rho, pr, u, phi_out);
-    LBM_DISPATCH(storage, tp, frc, CALL);
+    const bool tp = p.two_phase != 0, frc = p.n_modes > 0, ml = p.curv_mode == 1;
+#define CALL(S_, TP_, F_, M_) \
+    hipLaunchKernelGGL((k_moments<S_, TP_, F_, M_>), grid, block, 0, s, p, fin, phi, rho, pr, u, phi_out);
+    LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     return hipGetLastError();
 }
@@ -922,9 +1043,10 @@ hipError_t launch_reduce(const Params &p, int storage, const void *fin, const do
                          double *out, hipStream_t s)
 {
     dim3 grid(RED_BLOCKS), block(NTHREADS);
-    const bool tp = p.two_phase != 0, frc = p.n_modes > 0;
-#define CALL(S_, TP_, F_) hipLaunchKernelGGL((k_reduce<S_, TP_, F_>), grid, block, 0, s, p, fin, phi, partials);
-    LBM_DISPATCH(storage, tp, frc, CALL);
+    const bool tp = p.two_phase != 0, frc = p.n_modes > 0, ml = p.curv_mode == 1;
+#define CALL(S_, TP_, F_, M_) \
+    hipLaunchKernelGGL((k_reduce<S_, TP_, F_, M_>), grid, block, 0, s, p, fin, phi, partials);
+    LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

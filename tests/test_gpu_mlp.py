@@ -123,9 +123,7 @@ def test_adam_matches_oracle():
 def test_harvest_matches_oracle():
     lbm = _lbm()
     shape = (24, 28, 70)
-    phi0, c, r = I.bubble_pack(shape, 3, (6.0, 10.0), seed=12)
-    drop, cd = I.droplet(shape, 5.0, 4.0, center=(50.3, 8.2, 12.7))
-    phi = np.minimum(phi0, 1.0 - drop) * 0 + phi0  # bubbles only
+    phi, c, r = I.bubble_pack(shape, 3, (6.0, 10.0), seed=12)
     g = lbm.Lattice(shape, 0.8, phi0=phi, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
     radii = -r  # phi = 0 inside
     X, Y, n = g.harvest(c, radii, cap=1 << 16)
@@ -139,3 +137,41 @@ def test_harvest_matches_oracle():
     X2, Y2, n2 = g.harvest(c, radii, cap=100)
     assert n2 == n and len(X2) == 100
     np.testing.assert_array_equal(X2.cpu().numpy(), X[:100].cpu().numpy())
+
+
+def _mlp_case_weights(seed):
+    """Weights whose normal output is near unit length for part of the inputs,
+    so both the blended and the finite-difference fallback branches occur."""
+    w = _weights(seed, scale=0.25)
+    w[6208 + 1:6212] = [0.6, 0.5, 0.4]  # b3 for the normal outputs
+    return w.astype(np.float16).astype(np.float64)
+
+
+def test_step_with_learned_curvature_matches_oracle():
+    import torch
+
+    lbm = _lbm()
+    shape = (24, 20, 70)
+    phi_a, _ = I.droplet(shape, 3.0, 4.0, center=(20.3, 10.1, 12.2))
+    phi_b, _ = I.droplet(shape, 4.0, 4.0, center=(52.7, 9.6, 11.4))
+    phi0 = np.maximum(phi_a, phi_b)
+    u0 = I.random_u(shape, 0.005, seed=31)
+    w = _mlp_case_weights(32)
+    kw = dict(rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    g = lbm.Lattice(shape, 0.8, phi0=phi0, u0=u0, zchunk=8, curv_mode="mlp", **kw)
+    with pytest.raises(lbm.LbmError):
+        g.step(1)  # weights not installed yet
+    g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
+    g.step(30)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    o = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, curv_mode=1, mlp=w, **kw)
+    o.step(30)
+    mo = o.moments()
+    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    # the learned force differs from the finite-difference one (the test is not vacuous)
+    ofd = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, **kw)
+    ofd.step(30)
+    dfd = np.linalg.norm(ofd.moments()["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    print(f"learned-curvature step: u rel err {e:.3e} (FD vs learned oracle runs differ by {dfd:.3e})")
+    assert dfd > 1e-3
+    assert e < 1e-3
