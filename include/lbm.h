@@ -59,7 +59,7 @@ enum { LBM_CURV_FD = 0, LBM_CURV_MLP = 1 };
 typedef struct lbm_handle lbm_handle;
 
 typedef struct {
-    int32_t nx, ny, nz;  /* each >= 8, nx*ny*nz <= 2^30 */
+    int32_t nx, ny, nz;  /* each >= 8, nx*ny <= 2^24, nx*ny*nz <= 2^30 */
     int32_t storage;     /* LBM_STORE_* */
     int32_t two_phase;   /* 0: single phase (rho = rho_l, no phase field), 1: coupled Allen-Cahn */
     int32_t curv_mode;   /* LBM_CURV_*; LBM_CURV_MLP needs lbm_set_mlp before stepping */
@@ -72,7 +72,7 @@ typedef struct {
     int32_t n_modes;     /* forcing rows, 0 .. LBM_MAX_MODES */
     int32_t zchunk;      /* z planes per workgroup (0 = library default) */
     const double *modes; /* HOST table [n_modes][9]: kx ky kz Re(Ax) Im(Ax) Re(Ay) Im(Ay) Re(Az) Im(Az);
-                            integer wave numbers with |kz| <= 2; body acceleration
+                            integer wave numbers with |kx| <= 2; body acceleration
                             a(x) = sum_m Re(A_m exp(2 pi i (kx x/nx + ky y/ny + kz z/nz)));
                             read during lbm_init only */
     double mlp_k_lo;     /* MLP blend ramp on |K_FD| (defaults 0.4 .. 0.6 when both are 0) */

@@ -25,7 +25,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], fcol, fz, partials, red, mlp, sph, hcount, total;
+    size_t f[2], phi[2], u[2], frow, fx, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -49,10 +49,10 @@ Layout layout_of(const lbm_config &c)
         L.phi[0] = L.phi[1] = L.u[0] = L.u[1] = (size_t)-1;
     }
     if (c.n_modes > 0) {
-        L.fcol = take(sizeof(float) * lbm::FCOL * (size_t)c.nx * c.ny);
-        L.fz = take(sizeof(float) * 4 * (size_t)c.nz);
+        L.frow = take(sizeof(float) * lbm::FROW * (size_t)c.ny * c.nz);
+        L.fx = take(sizeof(float) * 4 * (size_t)c.nx);
     } else {
-        L.fcol = L.fz = (size_t)-1;
+        L.frow = L.fx = (size_t)-1;
     }
     L.partials = take(sizeof(double) * lbm::RED_BLOCKS * lbm::NRED);
     L.red = take(sizeof(double) * lbm::NRED);
@@ -69,6 +69,7 @@ const char *validate(const lbm_config *c)
     if (c->nx < 8 || c->ny < 8 || c->nz < 8) return "nx, ny, nz must be >= 8";
     const double N = (double)c->nx * c->ny * c->nz;
     if (N > 1073741824.0) return "nx*ny*nz must be <= 2^30";
+    if ((double)c->nx * c->ny > 16777216.0) return "nx*ny must be <= 2^24";
     if (c->storage < LBM_STORE_F32 || c->storage > LBM_STORE_BF16) return "storage must be F32, F16 or BF16";
     if (c->two_phase != 0 && c->two_phase != 1) return "two_phase must be 0 or 1";
     if (c->curv_mode != LBM_CURV_FD && c->curv_mode != LBM_CURV_MLP) return "curv_mode must be FD or MLP";
@@ -88,7 +89,7 @@ const char *validate(const lbm_config *c)
         const double *r = c->modes + 9 * m;
         for (int k = 0; k < 3; k++)
             if (r[k] != std::floor(r[k]) || std::fabs(r[k]) > 1024.0) return "mode wave numbers must be integers";
-        if (std::fabs(r[2]) > 2.0) return "mode kz must satisfy |kz| <= 2";
+        if (std::fabs(r[0]) > 2.0) return "mode kx must satisfy |kx| <= 2";
         for (int k = 3; k < 9; k++)
             if (!std::isfinite(r[k])) return "mode amplitudes must be finite";
     }
@@ -115,7 +116,7 @@ struct lbm_handle {
     int cur = 0;
     int64_t steps = 0;
     bool mlp_set = false;
-    std::vector<float> fcol_host, fz_host;
+    std::vector<float> frow_host, fx_host;
     std::string err;
 
     void *f(int k) { return ws + L.f[k]; }
@@ -203,74 +204,85 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
     P.k_lo = (float)lo;
     P.k_hi = (float)hi;
     P.mlp = h->ws + L.mlp;
-    P.fcol = nullptr;
-    P.fz = nullptr;
+    P.frow = nullptr;
+    P.fx = nullptr;
     P.gx = (cfg->nx + lbm::TX - 1) / lbm::TX;
     P.gy = (cfg->ny + lbm::TY - 1) / lbm::TY;
     P.gz = (cfg->nz + P.zchunk - 1) / P.zchunk;
     P.nblocks = P.gx * P.gy * P.gz;
 
     if (cfg->n_modes > 0) {
-        // body-force tables in FP64 on the host, stored as FP32
-        const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
-        const size_t plane = (size_t)nx * ny;
-        h->fcol_host.assign((size_t)lbm::FCOL * plane, 0.0f);
-        h->fz_host.assign((size_t)4 * nz, 0.0f);
-        std::vector<double> acc(lbm::FCOL);
+        // body-force tables in FP64 on the host, stored as FP32: per mode,
+        // B = A e^{i (ky ty + kz tz)} is folded into the row coefficients of
+        // cos(|kx| t) (Re B) and sin(|kx| t) (-sign(kx) Im B), t = 2 pi x / nx
+        const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, nm = cfg->n_modes;
+        h->frow_host.assign((size_t)lbm::FROW * ny * nz, 0.0f);
+        h->fx_host.assign((size_t)4 * nx, 0.0f);
         const double two_pi = 6.283185307179586476925286766559;
-        for (int y = 0; y < ny; y++)
-            for (int x = 0; x < nx; x++) {
-                std::fill(acc.begin(), acc.end(), 0.0);
-                for (int m = 0; m < cfg->n_modes; m++) {
+        auto twiddle = [&](long k, long v, long n, double &c, double &s) {
+            const long f = ((k * v) % n + n) % n;  // exact phase index
+            c = std::cos(two_pi * (double)f / n);
+            s = std::sin(two_pi * (double)f / n);
+        };
+        std::vector<double> ey(2 * (size_t)nm * ny), ez(2 * (size_t)nm * nz);
+        for (int m = 0; m < nm; m++) {
+            const double *r = cfg->modes + 9 * m;
+            for (int y = 0; y < ny; y++) twiddle((long)r[1], y, ny, ey[2 * ((size_t)m * ny + y)], ey[2 * ((size_t)m * ny + y) + 1]);
+            for (int z = 0; z < nz; z++) twiddle((long)r[2], z, nz, ez[2 * ((size_t)m * nz + z)], ez[2 * ((size_t)m * nz + z) + 1]);
+        }
+        double acc[lbm::FROW];
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++) {
+                std::fill(acc, acc + lbm::FROW, 0.0);
+                for (int m = 0; m < nm; m++) {
                     const double *r = cfg->modes + 9 * m;
-                    // Re(A e^{i k.x}) = Re(conj(A) e^{-i k.x}): use kz >= 0
-                    const double sg = r[2] < 0 ? -1.0 : 1.0;
-                    const long kx = (long)(sg * r[0]), ky = (long)(sg * r[1]), kz = (long)(sg * r[2]);
-                    const long fx = ((kx * x) % nx + nx) % nx, fy = ((ky * y) % ny + ny) % ny;
-                    const double th = two_pi * ((double)fx / nx + (double)fy / ny);
-                    const double cs = std::cos(th), sn = std::sin(th);
+                    const long kx = (long)r[0];
+                    const double *cy = &ey[2 * ((size_t)m * ny + y)], *cz = &ez[2 * ((size_t)m * nz + z)];
+                    const double pc = cy[0] * cz[0] - cy[1] * cz[1], ps = cy[0] * cz[1] + cy[1] * cz[0];
+                    const int kk = (int)(kx < 0 ? -kx : kx);
+                    const double sg = kx < 0 ? -1.0 : 1.0;
                     for (int a = 0; a < 3; a++) {
-                        const double ar = r[3 + 2 * a], ai = sg * r[4 + 2 * a];
-                        const double re = ar * cs - ai * sn, im = ar * sn + ai * cs;
-                        if (kz == 0) {
-                            acc[a] += re;
-                        } else if (kz == 1) {
-                            acc[3 + a] += re;
-                            acc[6 + a] += im;
+                        const double ar = r[3 + 2 * a], ai = r[4 + 2 * a];
+                        const double br = ar * pc - ai * ps, bi = ar * ps + ai * pc;
+                        if (kk == 0) {
+                            acc[a] += br;
                         } else {
-                            acc[9 + a] += re;
-                            acc[12 + a] += im;
+                            acc[3 + 6 * (kk - 1) + a] += br;
+                            acc[6 + 6 * (kk - 1) + a] -= sg * bi;
                         }
                     }
                 }
-                for (int k = 0; k < lbm::FCOL; k++) h->fcol_host[(size_t)k * plane + (size_t)y * nx + x] = (float)acc[k];
+                float *dst = &h->frow_host[((size_t)z * ny + y) * lbm::FROW];
+                for (int k = 0; k < lbm::FROW; k++) dst[k] = (float)acc[k];
             }
-        for (int z = 0; z < nz; z++) {
-            const double t = two_pi * (double)z / nz;
-            h->fz_host[4 * z + 0] = (float)std::cos(t);
-            h->fz_host[4 * z + 1] = (float)std::sin(t);
-            h->fz_host[4 * z + 2] = (float)std::cos(2.0 * t);
-            h->fz_host[4 * z + 3] = (float)std::sin(2.0 * t);
+        for (int x = 0; x < nx; x++) {
+            double c, s;
+            twiddle(1, x, nx, c, s);
+            h->fx_host[4 * x + 0] = (float)c;
+            h->fx_host[4 * x + 1] = (float)s;
+            twiddle(2, x, nx, c, s);
+            h->fx_host[4 * x + 2] = (float)c;
+            h->fx_host[4 * x + 3] = (float)s;
         }
-        float *dcol = (float *)(h->ws + L.fcol);
-        float4 *dz = (float4 *)(h->ws + L.fz);
-        hipError_t e = hipMemcpyAsync(dcol, h->fcol_host.data(), sizeof(float) * h->fcol_host.size(),
+        float *drow = (float *)(h->ws + L.frow);
+        float4 *dx = (float4 *)(h->ws + L.fx);
+        hipError_t e = hipMemcpyAsync(drow, h->frow_host.data(), sizeof(float) * h->frow_host.size(),
                                       hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(dz, h->fz_host.data(), sizeof(float) * h->fz_host.size(), hipMemcpyHostToDevice,
+            e = hipMemcpyAsync(dx, h->fx_host.data(), sizeof(float) * h->fx_host.size(), hipMemcpyHostToDevice,
                                h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging is released below
-        h->fcol_host.clear();
-        h->fcol_host.shrink_to_fit();
-        h->fz_host.clear();
-        h->fz_host.shrink_to_fit();
+        h->frow_host.clear();
+        h->frow_host.shrink_to_fit();
+        h->fx_host.clear();
+        h->fx_host.shrink_to_fit();
         if (e != hipSuccess) {
             g_init_err = std::string("forcing table upload: ") + hipGetErrorString(e);
             delete h;
             return LBM_EHIP;
         }
-        P.fcol = dcol;
-        P.fz = dz;
+        P.frow = drow;
+        P.fx = dx;
     }
     hipError_t e = lbm::launch_init(P, cfg->storage, h->f(0), h->phi(0), h->u(0), d_phi0, d_u0, d_pstar0, h->stream);
     if (e != hipSuccess) {

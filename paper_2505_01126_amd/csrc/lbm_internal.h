@@ -16,13 +16,14 @@ constexpr int MAX_MODES = 64;
 constexpr int NRED = 10;
 constexpr int RED_BLOCKS = 1024;  // fixed grid of the reduction (deterministic order)
 
-// Body-force tables, built on the host from the mode table (kz in 0..2 after
-// mapping kz < 0 rows to (-k, conj A)):
-//   fcol [15][ny * nx] floats, per column (x, y): Re C0 (3), Re C1 (3), Im C1 (3),
-//        Re C2 (3), Im C2 (3) with C_k = sum_{rows with kz = k} A e^{2 pi i (kx x/nx + ky y/ny)};
-//   fz   [nz] float4: cos, sin of 2 pi z/nz and of 4 pi z/nz.
-// a(x, y, z) = Re C0 + Re(C1 t) + Re(C2 t^2), t = e^{2 pi i z/nz}.
-constexpr int FCOL = 15;
+// Body-force tables, built on the host in FP64 from the mode table (|kx| <= 2)
+// and stored as FP32:
+//   frow [nz * ny][16] per x-row (y, z): P0 (3), P1 (3), Q1 (3), P2 (3), Q2 (3), pad,
+//        the coefficients of a(x) = P0 + P1 cos t + Q1 sin t + P2 cos 2t + Q2 sin 2t
+//        with t = 2 pi x / nx (modes grouped by |kx|, the y and z phases folded in);
+//   fx   [nx] float4: cos t, sin t, cos 2t, sin 2t.
+// A workgroup row is one wave, so the row coefficients are wave-uniform.
+constexpr int FROW = 16;
 
 // Scalar parameters of one configuration, passed by value to every kernel.
 struct Params {
@@ -37,8 +38,8 @@ struct Params {
     float d6;       // 6 D     (diffusion link coefficient, times w_i)
     float k3;       // 3 kappa (sharpening link coefficient, times w_i)
     float k_lo, k_hi;
-    const float *fcol;       // device forcing column table, or nullptr
-    const float4 *fz;        // device forcing plane twiddles, or nullptr
+    const float *frow;       // device forcing row table, or nullptr
+    const float4 *fx;        // device forcing x twiddles, or nullptr
     const void *mlp;         // device fp16 weights, or nullptr
 };
 

@@ -1,13 +1,16 @@
 // Hand-written gfx950 kernels of one accLB time step (arXiv 2505.01126, Secs. 2-3).
 //
 // k_step fuses, per lattice site and time step:
-//   pull-streaming of the 27 D3Q27 populations (SoA, one coalesced row per
-//   direction), their moments, the phase-field stencils (LDS-staged phi tile),
+//   pull-streaming of the 27 D3Q27 populations (structure of arrays, one
+//   coalesced row per direction), their moments, the phase-field stencils (LDS-staged phi tile),
 //   the forces of Eq. (8), the regularised collision of Eqs. (6)-(7) rebuilt
 //   from p*, u and a^(2) (each site writes only its own slots, Sec. 3), and the
 //   conservative Allen-Cahn update of Eq. (3).
 //
-// Populations are stored as h_i = f_i / w_i - P0 in FP32, FP16 or BF16; all
+// Populations are stored as h_i = f_i / w_i - P0 in FP32, FP16 or BF16, plane
+// by plane: population i of site (x, y, z) at ((z * 27 + i) * ny + y) * nx + x,
+// so the 27 rows a site reads or writes lie within 3 x 27 planes and are
+// addressed from one per-plane base pointer with 32-bit offsets; all
 // arithmetic is FP32.  Each phase-field flux through a face or lattice link is
 // evaluated by contraction-free code from identical operands on both sides of
 // the link (or once, shared through LDS), so the two sites see bit-identical
@@ -66,6 +69,14 @@ __device__ __forceinline__ int modi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// element index of population i at site s (plane-major population layout)
+__device__ __forceinline__ size_t pop_index(const Params &P, int i, uint32_t s)
+{
+    const uint32_t plane = (uint32_t)P.nx * P.ny;
+    const uint32_t z = s / plane, xy = s - z * plane;
+    return ((size_t)z * 27 + i) * plane + xy;
+}
+
 // element at a 32-bit byte offset from a uniform base: lets the compiler use
 // the scalar-base + 32-bit vector-offset addressing of global memory
 template <class T> __device__ __forceinline__ T ldb(const void *base, uint32_t byte_off)
@@ -75,6 +86,28 @@ template <class T> __device__ __forceinline__ T ldb(const void *base, uint32_t b
 template <class T> __device__ __forceinline__ void stb(void *base, uint32_t byte_off, T v)
 {
     *(T *)((char *)base + byte_off) = v;
+}
+
+// Raw buffer access to one z plane of populations (27 rows of nx * ny): the
+// row offset i * plane goes in the scalar offset, the in-plane offset in the
+// vector offset, so no per-row vector address arithmetic is needed.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <class T> __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
 }
 
 // ------------------------------------------------------ separable moments
@@ -168,7 +201,7 @@ __device__ __forceinline__ void surface_fd(const PhiGrad &G, const Params &P, fl
         const float gHg = g[0] * (H[0] * g[0] + H[3] * g[1] + H[4] * g[2]) +
                           g[1] * (H[3] * g[0] + H[1] * g[1] + H[5] * g[2]) +
                           g[2] * (H[4] * g[0] + H[5] * g[1] + H[2] * g[2]);
-        cs = -P.fs_coef * (trH - gHg / g2);
+        cs = -P.fs_coef * (trH - gHg * __builtin_amdgcn_rcpf(g2));
     }
 #pragma unroll
     for (int a = 0; a < 3; a++) fs[a] = cs * g[a];
@@ -244,7 +277,7 @@ __device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const
         const float *g = G.g;
         const float drho = P.rho_l - P.rho_g;
         const float cp = -(P.p0 + m.dp) * (1.0f / 3.0f) * drho;  // F^p = cp * g
-        const float inv_rho = 1.0f / rho;
+        const float inv_rho = __builtin_amdgcn_rcpf(rho);
         float F[3], u0[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -363,18 +396,26 @@ __device__ __forceinline__ float face_flux(float v0, float v1, float v2, float v
 }
 
 // Diffusion + sharpening flux leaving a toward b = a + c_I (canonical I > 13):
-// w_I [6 D (phi_a - phi_b) + 3 kappa (Q_a + Q_b) . c_I]
+// w_I [6 D (phi_a - phi_b) + 3 kappa (Q_a + Q_b) . c_I]; the projection on c_I
+// takes the nonzero components in x, y, z order.
 template <int I>
-__device__ __forceinline__ float link_flux(float pa, float pb, const float *qa, const float *qb, float d6w, float k3w)
+__device__ __forceinline__ float link_flux(float pa, float pb, const float4 &qa, const float4 &qb, float d6w,
+                                           float k3w)
 {
 #pragma clang fp contract(off)
-    float s = 0.0f;
-    if constexpr (CX(I) > 0) s = s + (qa[0] + qb[0]);
-    if constexpr (CX(I) < 0) s = s - (qa[0] + qb[0]);
-    if constexpr (CY(I) > 0) s = s + (qa[1] + qb[1]);
-    if constexpr (CY(I) < 0) s = s - (qa[1] + qb[1]);
-    if constexpr (CZ(I) > 0) s = s + (qa[2] + qb[2]);
-    if constexpr (CZ(I) < 0) s = s - (qa[2] + qb[2]);
+    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
+    const float tx = qa.x + qb.x, ty = qa.y + qb.y, tz = qa.z + qb.z;
+    float s;
+    if constexpr (cx != 0) {
+        s = cx > 0 ? tx : -tx;
+        if constexpr (cy != 0) s = cy > 0 ? s + ty : s - ty;
+        if constexpr (cz != 0) s = cz > 0 ? s + tz : s - tz;
+    } else if constexpr (cy != 0) {
+        s = cy > 0 ? ty : -ty;
+        if constexpr (cz != 0) s = cz > 0 ? s + tz : s - tz;
+    } else {
+        s = cz > 0 ? tz : -tz;
+    }
     return fmaf(k3w, s, d6w * (pa - pb));
 }
 
@@ -412,25 +453,15 @@ __device__ __forceinline__ void q_of(const float (&v)[27], float (&q)[3])
 
 // ----------------------------------------------------------------- forcing
 // Time-independent body acceleration (Sec. 5.1 uses a fixed large-scale
-// field).  The host tabulates, per (x, y) column, the sums C_k over the mode
-// rows with kz = k (see lbm_internal.h); per plane a = Re C0 + Re(C1 t) + Re(C2 t^2).
-struct Forcing {
-    float c[FCOL];
-};
-
-__device__ __forceinline__ void forcing_column(const Params &P, uint32_t xy, Forcing &F)
+// field).  The host groups the modes by |kx| and folds the y and z phases into
+// per-row coefficients (see lbm_internal.h); a site combines its row's 15
+// coefficients with the x twiddles ex = (cos t, sin t, cos 2t, sin 2t).
+__device__ __forceinline__ void forcing_at(const Params &P, float4 ex, uint32_t row, float (&a)[3])
 {
-    const uint32_t plane = (uint32_t)P.nx * P.ny;
-#pragma unroll
-    for (int k = 0; k < FCOL; k++) F.c[k] = P.fcol[k * plane + xy];
-}
-
-__device__ __forceinline__ void forcing_at(const Forcing &F, const Params &P, int z, float (&a)[3])
-{
-    const float4 t = P.fz[z];  // cos 2pi z/nz, sin, cos 4pi z/nz, sin
+    const float *r = P.frow + (size_t)row * FROW;
 #pragma unroll
     for (int d = 0; d < 3; d++)
-        a[d] = F.c[d] + (F.c[3 + d] * t.x - F.c[6 + d] * t.y) + (F.c[9 + d] * t.z - F.c[12 + d] * t.w);
+        a[d] = r[d] + (r[3 + d] * ex.x + r[6 + d] * ex.y) + (r[9 + d] * ex.z + r[12 + d] * ex.w);
 }
 
 // ------------------------------------------------------------ fused step
@@ -462,10 +493,16 @@ __device__ __forceinline__ void lds_barrier()
 // Software pipeline over the z planes of a chunk: while plane z is processed,
 // the phi plane z+4, the face velocities of plane z+1, the 27 populations of
 // plane z+1 and the site's own phi and u_z ahead are already being fetched.
+#ifndef LBM_PF_LATE_MASK
+#define LBM_PF_LATE_MASK 0
+#endif
 template <int S, bool TP, bool FRC, bool ML>
 __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 {
     using T = typename Pop<S>::T;
+    // storage types (bit S) whose next-plane populations are fetched after the
+    // phase-field work rather than before it (shorter register live range)
+    constexpr bool kLatePrefetch = TP && ((LBM_PF_LATE_MASK >> S) & 1);
     constexpr uint32_t ES = sizeof(T);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
@@ -498,25 +535,28 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
             src_xy[(dy + 1) * 3 + dx + 1] = (uint32_t)wrapi(yg - dy, ny) * nx + (uint32_t)wrapi(xg - dx, nx);
     const uint32_t own_xy = (uint32_t)yg * nx + xg;
 
-    Forcing frc;
-    if constexpr (FRC) forcing_column(P, own_xy, frc);
+    float4 ex = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (FRC) ex = P.fx[xg];
+    // a wave is one x-row: its y is uniform
+    const uint32_t yrow = (uint32_t)__builtin_amdgcn_readfirstlane(yg);
 
     // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
     float hv[27];
+    const size_t pstride = (size_t)27 * plane;  // elements per z plane of populations
+    const uint32_t pbytes = 27u * plane * ES;   // bytes per z plane of populations
     auto fetch_pops = [&](int z) {
-        const uint32_t zsrc[3] = {(uint32_t)wrapi(z + 1, nz) * plane, (uint32_t)z * plane,
-                                  (uint32_t)wrapi(z - 1, nz) * plane};
+        const __amdgpu_buffer_rsrc_t zsrc[3] = {plane_rsrc(fin + (size_t)wrapi(z + 1, nz) * pstride, pbytes),
+                                                plane_rsrc(fin + (size_t)z * pstride, pbytes),
+                                                plane_rsrc(fin + (size_t)wrapi(z - 1, nz) * pstride, pbytes)};
 #pragma unroll
-        for (int i = 0; i < 27; i++) {
-            const uint32_t s = zsrc[CZ(i) + 1] + src_xy[(CY(i) + 1) * 3 + CX(i) + 1];
-            hv[i] = Pop<S>::dec(ldb<T>(fin + (size_t)i * N, s * ES));
-        }
+        for (int i = 0; i < 27; i++)
+            hv[i] = Pop<S>::dec(bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, i * plane * ES));
     };
 
     // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
     // the global xy offset of every position of the phi tile
     __shared__ float sphi[TP ? NRING : 1][TP ? PLANE : 1];
-    __shared__ float sq[TP ? 3 : 1][3][TP ? QPLANE : 1];
+    __shared__ float4 sq[TP ? 3 : 1][TP ? QPLANE : 1];  // Q (x, y, z, unused) per point
     __shared__ float sjx[TP ? NXF : 1];
     __shared__ float sjy[TP ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
@@ -581,9 +621,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                 }
                 float q[3];
                 q_of(st, q);
-                sq[slot][0][p] = q[0];
-                sq[slot][1][p] = q[1];
-                sq[slot][2][p] = q[2];
+                sq[slot][p] = make_float4(q[0], q[1], q[2], 0.0f);
             }
         }
     };
@@ -675,19 +713,20 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
         bool sel = false;
         if (active) {
             moments10(hv, M);
-            if (more) fetch_pops(z + 1);
+            if (!kLatePrefetch && more) fetch_pops(z + 1);
 
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
-                double acc = 0.0;
-                acc += (double)sjx[ty * (TX + 1) + tx] - (double)sjx[ty * (TX + 1) + tx + 1];
-                acc += (double)sjy[ty * TX + tx] - (double)sjy[(ty + 1) * TX + tx];
+                // four independent FP64 partial sums keep the dependent add chains short
+                double acc[4];
+                acc[0] = (double)sjx[ty * (TX + 1) + tx] - (double)sjx[ty * (TX + 1) + tx + 1];
+                acc[0] += (double)sjy[ty * TX + tx] - (double)sjy[(ty + 1) * TX + tx];
                 {
                     float v[6];
 #pragma unroll
                     for (int k = 0; k < 6; k++) v[k] = sphi[ring(z - 2 + k)][lc];
                     const float jr = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], uz_c, uz_n);
-                    acc += (double)jz_left - (double)jr;
+                    acc[1] = (double)jz_left - (double)jr;
                     jz_left = jr;
                     uz_c = uz_n;
                     if (more) uz_n = uz_in[(uint32_t)wrapi(z + 2, nz) * plane + own_xy];
@@ -704,29 +743,31 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                     }
                     phi_stencil(ph, G);
                     if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
-                    const float *q0 = sq[(z - 1 + 3) % 3][0];
-                    const float *q1 = sq[(z + 3) % 3][0];
-                    const float *q2 = sq[(z + 1 + 3) % 3][0];
-                    const float qo[3] = {q1[qc], q1[qc + QPLANE], q1[qc + 2 * QPLANE]};
+                    const float4 *q0 = sq[(z - 1 + 3) % 3];
+                    const float4 *q1 = sq[(z + 3) % 3];
+                    const float4 *q2 = sq[(z + 1 + 3) % 3];
+                    const float4 qo = q1[qc];
                     const float d6w[4] = {0.f, P.d6 * WT(14), P.d6 * WT(15), P.d6 * WT(26)};
                     const float k3w[4] = {0.f, P.k3 * WT(14), P.k3 * WT(15), P.k3 * WT(26)};
+                    // links 14 and 15 open the partial sums 2 and 3
 #define LB_LINK(I)                                                                                    \
     {                                                                                                 \
-        const float *qp = (CZ(I) > 0 ? q2 : q1) + qc + CY(I) * QX + CX(I);                            \
-        const float *qm = (CZ(I) > 0 ? q0 : q1) + qc - CY(I) * QX - CX(I);                            \
-        const float qn[3] = {qp[0], qp[QPLANE], qp[2 * QPLANE]};                                      \
-        const float qs[3] = {qm[0], qm[QPLANE], qm[2 * QPLANE]};                                      \
+        const float4 qn = (CZ(I) > 0 ? q2 : q1)[qc + CY(I) * QX + CX(I)];                             \
+        const float4 qs = (CZ(I) > 0 ? q0 : q1)[qc - CY(I) * QX - CX(I)];                             \
         const float fo = link_flux<I>(ph[13], ph[I], qo, qn, d6w[C2(I)], k3w[C2(I)]);                 \
         const float fi = link_flux<I>(ph[26 - I], ph[13], qs, qo, d6w[C2(I)], k3w[C2(I)]);            \
-        acc += (double)fi - (double)fo;                                                               \
+        const double d = (double)fi - (double)fo;                                                     \
+        if constexpr (I == 14 || I == 15) acc[I & 3] = d;                                             \
+        else acc[I & 3] += d;                                                                         \
     }
                     LB_LINK(14) LB_LINK(15) LB_LINK(16) LB_LINK(17) LB_LINK(18) LB_LINK(19) LB_LINK(20)
                     LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
                 }
-                B.phout[(size_t)own] = po + acc;
+                B.phout[(size_t)own] = po + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
                 if (more) po = B.phin[(size_t)own + plane];
             }
+            if (kLatePrefetch && more) fetch_pops(z + 1);
         }
         // surface tension: finite differences, or blended with the network
         // evaluated on the wave's selected interface cells (all lanes together)
@@ -743,7 +784,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
         }
         if (active) {
             float aext[3] = {0.f, 0.f, 0.f};
-            if constexpr (FRC) forcing_at(frc, P, z, aext);
+            if constexpr (FRC) forcing_at(P, ex, (uint32_t)z * ny + yrow, aext);
 
             // moments -> forces, velocity
             Macro m;
@@ -752,8 +793,9 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
             // regularised collision, written to this site's own slots
             float h[27];
             collide(m, P.omega, h);
+            const __amdgpu_buffer_rsrc_t dst = plane_rsrc(fout + (size_t)z * pstride, pbytes);
 #pragma unroll
-            for (int i = 0; i < 27; i++) stb<T>(fout + (size_t)i * N, own * ES, Pop<S>::enc(h[i]));
+            for (int i = 0; i < 27; i++) bstore<T>(dst, own_xy * ES, i * plane * ES, Pop<S>::enc(h[i]));
 
             if constexpr (TP) {  // velocity of this step, advects phi in the next one
                 stb<float>(B.uout, own * 4u, m.u[0]);
@@ -809,7 +851,7 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) hA += (c[a] * c[b] - (a == b ? 1.0 / 3.0 : 0.0)) * A[a][b];
         const double h = dp + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2 + 4.5 * hA;
-        fout[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))] = Pop<S>::enc((float)h);
+        fout[pop_index(P, i, nb(-CX(i), -CY(i), -CZ(i)))] = Pop<S>::enc((float)h);
     }
     if (phi_out) phi_out[s] = P.two_phase ? phi0[s] : 0.0;
     if (u_out)
@@ -840,7 +882,7 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     if (valid) {
         float hv[27];
 #pragma unroll
-        for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[(size_t)i * N + nb(-CX(i), -CY(i), -CZ(i))]);
+        for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[pop_index(P, i, nb(-CX(i), -CY(i), -CZ(i)))]);
         moments10(hv, M);
         if constexpr (TP) {
 #pragma unroll
@@ -863,9 +905,7 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     if (valid) {
         float aext[3] = {0.f, 0.f, 0.f};
         if constexpr (FRC) {
-            Forcing F;
-            forcing_column(P, (uint32_t)y * nx + x, F);
-            forcing_at(F, P, z, aext);
+            forcing_at(P, P.fx[x], (uint32_t)z * ny + y, aext);
         }
         site_macro<TP>(M, G, fs, aext, P, m);
     }

@@ -40,61 +40,73 @@ def _sphere_field(shape, centers, radii, width, bubbles):
     return 1.0 - phi_in if bubbles else phi_in
 
 
-def generate(n_boxes=24, box=48, per_box=4, r_min=2.0, r_max=10.0, relax=300, seed=0, device="cuda:0"):
+def _place(rng, box, per_box, r_min, r_max, width):
+    centers, radii = [], []
+    tries = 0
+    while len(radii) < per_box and tries < 10000:
+        tries += 1
+        r = rng.uniform(r_min, r_max)
+        c = rng.uniform(0, box, 3)
+        ok = True
+        for c2, r2 in zip(centers, radii):
+            d = c - c2
+            d -= box * np.round(d / box)
+            if np.linalg.norm(d) < r + r2 + 3 * width:
+                ok = False
+                break
+        if ok:
+            centers.append(c)
+            radii.append(r)
+    return np.array(centers), np.array(radii)
+
+
+def relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device="cuda:0"):
+    """One periodic box of spheres relaxed by the coupled solver.  Returns the
+    device Lattice (caller closes it), the FP64 phase field, the centres and
+    the signed volume-equivalent radii (negative for bubbles)."""
+    shape = (box, box, box)
+    centers, radii = _place(rng, box, per_box, r_min, r_max, PARAMS["width"])
+    phi0 = _sphere_field(shape, centers, radii, PARAMS["width"], bubbles)
+    g = lbm.Lattice(shape, 1.0, phi0=phi0, device=device, **PARAMS)
+    g.step(relax)
+    phi = g.moments()["phi"].cpu().numpy()
+    # volume-equivalent radius of each relaxed sphere (Voronoi by nearest centre)
+    z, y, x = I.grid(shape)
+    owner = np.zeros(shape, dtype=np.int64)
+    best = np.full(shape, np.inf)
+    for k, c in enumerate(centers):
+        d2 = 0.0
+        for a, coord in enumerate((x, y, z)):
+            dd = coord - c[a]
+            dd = dd - box * np.round(dd / box)
+            d2 = d2 + dd * dd
+        better = d2 < best
+        owner = np.where(better, k, owner)
+        best = np.where(better, d2, best)
+    inside = (1.0 - phi) if bubbles else phi
+    reff = np.array([(3.0 * float(inside[owner == k].sum()) / (4.0 * math.pi)) ** (1.0 / 3.0)
+                     for k in range(len(centers))])
+    return g, phi, centers, (-reff if bubbles else reff)
+
+
+def generate(n_boxes=24, box=48, per_box=4, r_min=2.0, r_max=10.0, relax=300, seed=0, device="cuda:0",
+             verbose=True):
     """Harvest training rows from relaxed method-generated spheres.
     Returns device tensors X [n, 32] (fp16 bits) and Y [n, 4] (FP32)."""
     import torch
 
     rng = np.random.default_rng(seed)
-    shape = (box, box, box)
     Xs, Ys = [], []
     for b in range(n_boxes):
         bubbles = bool(b % 2)
-        centers, radii = [], []
-        tries = 0
-        while len(radii) < per_box and tries < 10000:
-            tries += 1
-            r = rng.uniform(r_min, r_max)
-            c = rng.uniform(0, box, 3)
-            ok = True
-            for c2, r2 in zip(centers, radii):
-                d = c - c2
-                d -= box * np.round(d / box)
-                if np.linalg.norm(d) < r + r2 + 3 * PARAMS["width"]:
-                    ok = False
-                    break
-            if ok:
-                centers.append(c)
-                radii.append(r)
-        phi0 = _sphere_field(shape, centers, radii, PARAMS["width"], bubbles)
-        g = lbm.Lattice(shape, 1.0, phi0=phi0, device=device, **PARAMS)
-        g.step(relax)
-        phi = g.moments()["phi"].cpu().numpy()
-        # volume-equivalent radius of each relaxed sphere (Voronoi by nearest centre)
-        z, y, x = I.grid(shape)
-        owner = np.zeros(shape, dtype=np.int64)
-        best = np.full(shape, np.inf)
-        for k, c in enumerate(centers):
-            d2 = 0.0
-            for a, coord in enumerate((x, y, z)):
-                dd = coord - c[a]
-                dd = dd - box * np.round(dd / box)
-                d2 = d2 + dd * dd
-            better = d2 < best
-            owner = np.where(better, k, owner)
-            best = np.where(better, d2, best)
-        inside = (1.0 - phi) if bubbles else phi
-        reff = []
-        for k in range(len(centers)):
-            vol = float(inside[owner == k].sum())
-            reff.append((3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0))
-        signed = -np.array(reff) if bubbles else np.array(reff)
-        X, Y, n = g.harvest(np.array(centers), signed, cap=1 << 20)
+        g, _, centers, signed = relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device)
+        X, Y, n = g.harvest(centers, signed, cap=1 << 20)
         Xs.append(X.clone())
         Ys.append(Y.clone())
         g.close()
-        print(f"# box {b}: {'bubbles' if bubbles else 'droplets'} R={np.round(reff, 2).tolist()} -> {n} rows",
-              file=sys.stderr, flush=True)
+        if verbose:
+            print(f"# box {b}: {'bubbles' if bubbles else 'droplets'} R={np.round(np.abs(signed), 2).tolist()} "
+                  f"-> {n} rows", file=sys.stderr, flush=True)
     return torch.cat(Xs), torch.cat(Ys)
 
 

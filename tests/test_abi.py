@@ -47,7 +47,7 @@ def test_workspace_bytes_counts_state():
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)), dict(tau=0.8, storage="f16",
-                                                                                       modes=[[0, 0, 3] + [0] * 6])])
+                                                                                       modes=[[3, 0, 0] + [0] * 6])])
 def test_invalid_configs_rejected_on_host(kw):
     shape = kw.pop("shape", (16, 16, 16))
     tau = kw.pop("tau")
