@@ -10,8 +10,11 @@ rms 0.02.  Populations stored in FP32 (the reported value) and in FP16 / BF16
 (reported beside it); arithmetic is FP32 in every variant.
 
 A step is one fused kernel launch over the whole box.  Inputs are resident in
-HBM before timing starts; W untimed warm-up steps, then K timed steps between
-two stream synchronisations, timed with HIP events on the launch stream.
+HBM before timing starts; W untimed warm-up steps, then R blocks of K timed
+steps, each between two stream synchronisations and timed with HIP events on
+the launch stream; the median block is reported.  The learned-curvature
+variants run the same workload with the network blend switched on (seeded
+weights: the cost does not depend on their values).
 
 Prints one JSON line.  MLUPS = N * K / (t * 1e6).
 """
@@ -69,28 +72,65 @@ def traffic_for(workload_name, storage):
     return rec.get("bytes_per_launch")
 
 
-def time_variant(shape, phi0, u0, params, storage, steps, warmup, tau, zchunk):
+def mlp_weights(seed=5):
+    """Seeded network weights (fp16 bits) whose normal outputs are near unit
+    length, so the blend branch of the step runs."""
     import torch
 
     from paper_2505_01126_amd import lbm
 
-    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, **params)
+    w = np.random.default_rng(seed).standard_normal(lbm.MLP_NPARAM) * 0.25
+    w[-3:] = [0.6, 0.5, 0.4]
+    return torch.tensor(w.astype(np.float16).view(np.int16), device="cuda")
+
+
+def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, zchunk, curv="fd"):
+    import torch
+
+    from paper_2505_01126_amd import lbm
+
+    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, curv_mode=curv, **params)
+    if curv == "mlp":
+        g.set_mlp(mlp_weights())
     r0 = g.reduce()
     stream = g.stream
     g.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    g.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
     r1 = g.reduce()
     g.close()
     del g
     torch.cuda.empty_cache()
-    return ms / steps, r0, r1
+    return float(np.median(times)), r0, r1
+
+
+def copy_gbs(mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes) on this GPU."""
+    import torch
+
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (mib << 20) / dt / 1e9
 
 
 def cpu_baseline(seconds=15.0):
@@ -119,10 +159,14 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--storage", default="f32,f16,bf16")
+    ap.add_argument("--repeats", type=int, default=5)
+    ap.add_argument("--storage", default="f32,f16,bf16,f32:mlp,f16:mlp",
+                    help="comma list of storage[:curvature] variants; the first is the reported value")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bandwidth-probe", action="store_true",
+                    help="only run the streaming-kernel bandwidth probe (copy, read, write, 27-row) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 10 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -131,21 +175,22 @@ def main():
               "(the z-slab multi-GPU layout is described in the design notes but not built)", file=sys.stderr)
         sys.exit(2)
 
+    if args.bandwidth_probe:
+        import subprocess
+
+        probe = os.path.join(ROOT, "paper_2505_01126_amd", "bw_probe")
+        if not os.path.exists(probe):
+            print("bench.py: bw_probe is not built (run __graft_entry__.build())", file=sys.stderr)
+            sys.exit(1)
+        sys.exit(subprocess.call([probe]))
+
     import torch
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.copy_mib > 0:
-        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 10
-        print(json.dumps({"copy_mib": args.copy_mib, "copy_gbs": 2 * a.numel() / dt / 1e9}), flush=True)
+        print(json.dumps({"copy_mib": args.copy_mib, "copy_gbs": copy_gbs(args.copy_mib)}), flush=True)
         return
     t_setup = time.perf_counter()
     shape, phi0, u0, params, nb = workload(args.size)
@@ -155,20 +200,23 @@ def main():
     tau = 0.515
     name = f"bubbly_hit_{args.size}"
     variants = {}
-    for st in [s.strip() for s in args.storage.split(",") if s.strip()]:
-        ms, r0, r1 = time_variant(shape, phi0, u0, params, st, args.steps, args.warmup, tau, args.zchunk)
+    for key in [s.strip() for s in args.storage.split(",") if s.strip()]:
+        st, _, curv = key.partition(":")
+        curv = curv or "fd"
+        ms, r0, r1 = time_variant(shape, phi0, u0, params, st, args.steps, args.warmup, args.repeats, tau,
+                                  args.zchunk, curv)
         mlups = N / (ms * 1e-3) / 1e6
         achieved = BYTES_PER_LUP[st] * N / (ms * 1e-3) / 1e9
-        variants[st] = {
-            "mlups": mlups, "ms_per_step": ms, "bytes_per_lup": BYTES_PER_LUP[st],
+        variants[key] = {
+            "storage": st, "curvature": curv, "mlups": mlups, "ms_per_step": ms, "bytes_per_lup": BYTES_PER_LUP[st],
             "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS,
             "phase_volume_drift": abs(r1[0] - r0[0]) / r0[0], "nonfinite": int(r1[9]), "max_u": r1[7],
         }
-        print(f"# {st}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%})",
+        print(f"# {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%})",
               file=sys.stderr, flush=True)
-    primary = "f32" if "f32" in variants else next(iter(variants))
+    primary = next(iter(variants))
     v = variants[primary]
-    traffic = traffic_for(name, primary)
+    traffic = traffic_for(name, v["storage"]) if v["curvature"] == "fd" else None
     line = {
         "metric": "MLUPS & % HBM roofline, 512^3 bubbly HIT, FP32 vs FP16-stored populations",
         "value": v["mlups"],
@@ -183,11 +231,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": name, "grid": list(shape), "bubbles": nb, "bubble_diameter": 16,
-                   "density_ratio": 10, "sigma": 0.005, "tau": tau, "storage": primary,
-                   "curvature": "fd", "parallelism": "single GPU"},
+                   "density_ratio": 10, "sigma": 0.005, "tau": tau, "storage": v["storage"],
+                   "curvature": v["curvature"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": v["frac"], "traffic": traffic},
         "variants": variants,
+        "copy_gbs": copy_gbs(),
         "kernel_sha": kernel_sha(),
     }
     if not args.no_cpu_baseline:
