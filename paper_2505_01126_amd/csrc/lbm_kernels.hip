@@ -493,16 +493,15 @@ __device__ __forceinline__ void lds_barrier()
 // Software pipeline over the z planes of a chunk: while plane z is processed,
 // the phi plane z+4, the face velocities of plane z+1, the 27 populations of
 // plane z+1 and the site's own phi and u_z ahead are already being fetched.
-#ifndef LBM_PF_LATE_MASK
-#define LBM_PF_LATE_MASK 0
-#endif
 template <int S, bool TP, bool FRC, bool ML>
 __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 {
     using T = typename Pop<S>::T;
-    // storage types (bit S) whose next-plane populations are fetched after the
-    // phase-field work rather than before it (shorter register live range)
-    constexpr bool kLatePrefetch = TP && ((LBM_PF_LATE_MASK >> S) & 1);
+    // Where the next plane's populations are fetched: 16-bit values pack two
+    // to a register, so FP16/BF16 fetch right after the moments (longest
+    // prefetch distance) and still fit three waves per SIMD; FP32 fetches after
+    // the phase-field work, the shorter live range that fits three waves.
+    constexpr bool kLatePrefetch = TP && S == 0;
     constexpr uint32_t ES = sizeof(T);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
@@ -526,7 +525,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     const float *__restrict__ uy_in = B.uin + N;
     const float *__restrict__ uz_in = B.uin + 2 * (size_t)N;
 
-    // pull sources in the xy plane: index (cy+1)*3 + (cx+1) -> (x - cx, y - cy)
+    const int yw = __builtin_amdgcn_readfirstlane(yg);
     uint32_t src_xy[9];
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
@@ -537,11 +536,12 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 
     float4 ex = {0.f, 0.f, 0.f, 0.f};
     if constexpr (FRC) ex = P.fx[xg];
-    // a wave is one x-row: its y is uniform
-    const uint32_t yrow = (uint32_t)__builtin_amdgcn_readfirstlane(yg);
+    const uint32_t yrow = (uint32_t)yw;
 
     // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
-    float hv[27];
+    // raw storage values: decoded only where they are consumed, so the loads of
+    // the next plane stay in flight (a decode right after the load would wait for it)
+    T hv[27];
     const size_t pstride = (size_t)27 * plane;  // elements per z plane of populations
     const uint32_t pbytes = 27u * plane * ES;   // bytes per z plane of populations
     auto fetch_pops = [&](int z) {
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
                                                 plane_rsrc(fin + (size_t)wrapi(z - 1, nz) * pstride, pbytes)};
 #pragma unroll
         for (int i = 0; i < 27; i++)
-            hv[i] = Pop<S>::dec(bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, i * plane * ES));
+            hv[i] = bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, i * plane * ES);
     };
 
     // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
@@ -565,7 +565,6 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     MlpW &smw = *(MlpW *)mlp_raw;
     MlpWave *smwave = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
     if constexpr (ML) load_weights((const uint16_t *)P.mlp, smw, tid, NTHREADS);
-    uint32_t ld_xy[LOADS];
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
     bool f_isx[FROUNDS];
@@ -579,7 +578,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
-            if (e < PLANE) phn[k] = src[ld_xy[k]];
+            if (e < PLANE) phn[k] = src[sxy[e]];
         }
     };
     auto store_plane = [&](int z) {
@@ -650,8 +649,7 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
             const int ly = e / PX, lx = e - ly * PX;
-            ld_xy[k] = (uint32_t)modi(y0 + ly - HY, ny) * nx + (uint32_t)modi(x0 + lx - HX, nx);
-            if (e < PLANE) sxy[e] = ld_xy[k];
+            if (e < PLANE) sxy[e] = (uint32_t)modi(y0 + ly - HY, ny) * nx + (uint32_t)modi(x0 + lx - HX, nx);
         }
 #pragma unroll
         for (int k = 0; k < QPTS; k++) {
@@ -712,7 +710,12 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
         float kfd = 0.f, gn = 0.f;
         bool sel = false;
         if (active) {
-            moments10(hv, M);
+            {
+                float hf[27];
+#pragma unroll
+                for (int i = 0; i < 27; i++) hf[i] = Pop<S>::dec(hv[i]);
+                moments10(hf, M);
+            }
             if (!kLatePrefetch && more) fetch_pops(z + 1);
 
             if constexpr (TP) {

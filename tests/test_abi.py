@@ -46,8 +46,9 @@ def test_workspace_bytes_counts_state():
     assert two < 2 * 27 * 2 * N + 2 * 8 * N + 2 * 12 * N + (1 << 20)
 
 
-@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)), dict(tau=0.8, storage="f16",
-                                                                                       modes=[[3, 0, 0] + [0] * 6])])
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)),
+                                dict(tau=0.8, shape=(8, 4097, 4097)),
+                                dict(tau=0.8, storage="f16", modes=[[3, 0, 0] + [0] * 6])])
 def test_invalid_configs_rejected_on_host(kw):
     shape = kw.pop("shape", (16, 16, 16))
     tau = kw.pop("tau")
