@@ -110,6 +110,65 @@ def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, 
     return float(np.median(times)), r0, r1
 
 
+def batch_leg(steps, warmup, repeats, count=128, seed=3):
+    """Ensemble of `count` seeded bubble-in-box instances (edges 32..96, 1-8
+    bubbles of d 6-20, density ratio 1-10; FP16 populations, learned curvature
+    with finite-difference fallback; tau = 1, sigma = 0.01, at rest): aggregate
+    MLUPS of one launch per instance per step vs one persistent batched launch
+    per step (graph-replayed, z-chunk from the autotuner)."""
+    import torch
+
+    from paper_2505_01126_amd import inputs as I
+    from paper_2505_01126_amd import lbm
+
+    t0 = time.perf_counter()
+    ens = I.bubble_box_ensemble(count, seed=seed)
+    w16 = torch.tensor(mlp_weights().astype(np.float16).view(np.int16), device="cuda")
+    gs = []
+    for e in ens:
+        g = lbm.Lattice(e["shape"], 1.0, phi0=e["phi0"], rho_l=1.0, rho_g=1.0 / e["ratio"], sigma=0.01,
+                        mobility=0.05, width=4.0, p0=0.0, storage="f16", curv_mode="mlp")
+        g.set_mlp(w16)
+        gs.append(g)
+    sites = sum(g.N for g in gs)
+    print(f"# batch of {count} boxes ready in {time.perf_counter() - t0:.1f} s ({sites / 1e6:.1f} M sites)",
+          file=sys.stderr, flush=True)
+    stream = gs[0].stream
+
+    def timed(run):
+        times = []
+        for _ in range(repeats):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / steps)
+        return float(np.median(times))
+
+    def per_instance(k):
+        for _ in range(k):
+            for g in gs:
+                g.step(1)
+
+    per_instance(warmup)
+    ms_single = timed(lambda: per_instance(steps))
+    b = lbm.Batch(gs)
+    zc = b.tune(2)
+    b.step(warmup)
+    ms_batch = timed(lambda: b.step(steps))
+    b.close()
+    for g in gs:
+        g.close()
+    del gs
+    torch.cuda.empty_cache()
+    return {"instances": count, "sites": sites, "storage": "f16", "curvature": "mlp", "zchunk": zc,
+            "ms_per_step_batched": ms_batch, "ms_per_step_per_instance": ms_single,
+            "mlups_batched": sites / (ms_batch * 1e-3) / 1e6, "mlups_per_instance": sites / (ms_single * 1e-3) / 1e6,
+            "speedup": ms_single / ms_batch}
+
+
 def copy_gbs(mib=1024, reps=10):
     """Device-to-device copy bandwidth (read + write bytes) on this GPU."""
     import torch
@@ -163,6 +222,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 128-box ensemble leg")
     ap.add_argument("--bandwidth-probe", action="store_true",
                     help="only run the streaming-kernel bandwidth probe (copy, read, write, 27-row) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -237,6 +297,11 @@ def main():
         "copy_gbs": copy_gbs(),
         "kernel_sha": kernel_sha(),
     }
+    if not args.no_batch:
+        line["batch"] = batch_leg(min(args.steps, 50), min(args.warmup, 10), args.repeats)
+        bt = line["batch"]
+        print(f"# batch: {bt['mlups_batched']:.0f} MLUPS batched vs {bt['mlups_per_instance']:.0f} per instance "
+              f"({bt['speedup']:.2f}x), z-chunk {bt['zchunk']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -173,6 +173,51 @@ int lbm_set_mlp(lbm_handle *h, const uint16_t *d_w);
 int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int nb, uint16_t *d_x, float *d_y,
                 int64_t cap, int64_t *n_out);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent boxes advanced together: one persistent kernel launch per
+ * time step takes work items (box, xy tile, z chunk) from a queue, so boxes of
+ * uneven size share the GPU without one launch each; steps are replayed from
+ * a captured HIP graph.  Not in the paper (its runs are one box per job); it
+ * is the ensemble mode of this library.  A box advanced in a batch gives
+ * bit-identical fields to the same box advanced alone with lbm_step.
+ *
+ * Members are lbm_handle's created with lbm_init; they must share storage,
+ * two_phase, curv_mode and the presence of a body force, and be on the same
+ * stream (the first member's).  They must outlive the batch.  A member may
+ * still be stepped, read or reduced on its own; the batch picks up its state
+ * at the next lbm_batch_step. */
+#define LBM_BATCH_MAX 4096
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes of the batch tables for n members (0 if n is out of range). */
+size_t lbm_batch_bytes(int n);
+
+/* Create a batch of n members (1 <= n <= LBM_BATCH_MAX).  d_table: caller's
+ * device buffer of table_bytes >= lbm_batch_bytes(n), 256-byte aligned, owned
+ * by the caller and used by the batch until lbm_batch_destroy.  Errors:
+ * LBM_EINVAL (n, NULL or repeated member, mixed storage / two_phase /
+ * curv_mode / forcing / stream), LBM_ENOSPACE, LBM_EHIP. */
+int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d_table, size_t table_bytes);
+
+/* Advance every member by nsteps (>= 0), asynchronously on the members' stream.
+ * Pairs of steps replay a captured graph of two launches.  LBM_ESTATE if an
+ * MLP member has no weights. */
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Autotuner: time steps_per_candidate (>= 1) steps, after one warm-up step,
+ * for each z-chunk length in {8, 16, 32, 64} and keep the fastest, cached per
+ * set of member shapes for the life of the process (a cached set is not timed
+ * again).  The timed steps advance the members like lbm_batch_step.  Waits for
+ * the stream.  *zchunk_out (host, may be NULL) gets the chosen length. */
+int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out);
+
+/* Free the host-side batch (not the members, not d_table). */
+int lbm_batch_destroy(lbm_batch *b);
+
+/* Text of the latest failure on b, or of the latest failed lbm_batch_create
+ * when b is NULL. */
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 /* Static text for an error code. */
 const char *lbm_strerror(int code);
 

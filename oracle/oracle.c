@@ -438,27 +438,38 @@ struct orc_state {
     double *mlp;    /* private copy */
 };
 
-/* body acceleration a(x) = sum_m Re(A_m exp(i 2 pi (kx x/nx + ky y/ny + kz z/nz))) */
+/* body acceleration a(x) = sum_m Re(A_m exp(i 2 pi (kx x/nx + ky y/ny + kz z/nz))) of an
+ * nx x ny x nz periodic box, evaluated on the window of wx x wy x wz sites whose first
+ * site is (ox, oy, oz) (global coordinates taken modulo the box); out [3][wz][wy][wx] */
+void orc_forcing_window(const double *modes, int n_modes, int nx, int ny, int nz, int ox, int oy, int oz, int wx,
+                        int wy, int wz, double *out)
+{
+    const long W = (long)wx * wy * wz;
+    memset(out, 0, sizeof(double) * 3 * W);
+#pragma omp parallel for
+    for (long k = 0; k < wz; k++)
+        for (long j = 0; j < wy; j++)
+            for (long i = 0; i < wx; i++) {
+                const long x = ((ox + i) % nx + nx) % nx, y = ((oy + j) % ny + ny) % ny, z = ((oz + k) % nz + nz) % nz;
+                const long st = (k * wy + j) * wx + i;
+                for (int m = 0; m < n_modes; m++) {
+                    const double *r = modes + 9 * m;
+                    double th = 2.0 * M_PI * (r[0] * x / nx + r[1] * y / ny + r[2] * z / nz);
+                    double c = cos(th), sn = sin(th);
+                    for (int a = 0; a < 3; a++)
+                        out[a * W + st] += r[3 + 2 * a] * c - r[4 + 2 * a] * sn;
+                }
+            }
+}
+
 static void eval_forcing(orc_state *s)
 {
     const orc_params *p = &s->p;
-    long N = s->N;
-    memset(s->aext, 0, sizeof(double) * 3 * N);
-    if (p->n_modes <= 0)
+    if (p->n_modes <= 0) {
+        memset(s->aext, 0, sizeof(double) * 3 * s->N);
         return;
-#pragma omp parallel for
-    for (long z = 0; z < p->nz; z++)
-        for (long y = 0; y < p->ny; y++)
-            for (long x = 0; x < p->nx; x++) {
-                long st = site(p->nx, p->ny, x, y, z);
-                for (int m = 0; m < p->n_modes; m++) {
-                    const double *r = s->modes + 9 * m;
-                    double th = 2.0 * M_PI * (r[0] * x / p->nx + r[1] * y / p->ny + r[2] * z / p->nz);
-                    double c = cos(th), sn = sin(th);
-                    for (int a = 0; a < 3; a++)
-                        s->aext[a * N + st] += r[3 + 2 * a] * c - r[4 + 2 * a] * sn;
-                }
-            }
+    }
+    orc_forcing_window(s->modes, p->n_modes, p->nx, p->ny, p->nz, 0, 0, 0, p->nx, p->ny, p->nz, s->aext);
 }
 
 /* fp16 round-to-nearest-even of a double (IEEE binary16: 10 fraction bits,
@@ -888,6 +899,7 @@ void orc_reduce(const orc_state *s, double out[ORC_NRED])
 void orc_get_f(const orc_state *s, double *f) { memcpy(f, s->f, sizeof(double) * Q * s->N); }
 void orc_set_f(orc_state *s, const double *f) { memcpy(s->f, f, sizeof(double) * Q * s->N); }
 void orc_get_uprev(const orc_state *s, double *u) { memcpy(u, s->uprev, sizeof(double) * 3 * s->N); }
+void orc_set_aext(orc_state *s, const double *a) { memcpy(s->aext, a, sizeof(double) * 3 * s->N); }
 long orc_steps_done(const orc_state *s) { return s->steps; }
 
 int orc_threads(void)

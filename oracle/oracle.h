@@ -72,6 +72,11 @@ void orc_reduce(const orc_state *s, double out[ORC_NRED]);
 void orc_get_f(const orc_state *s, double *f);
 void orc_set_f(orc_state *s, const double *f);
 void orc_get_uprev(const orc_state *s, double *u);
+/* replace the body acceleration field [3][N] (e.g. a window of a larger box's forcing) */
+void orc_set_aext(orc_state *s, const double *a);
+/* the mode-table body acceleration of an nx x ny x nz box on a window of it (see oracle.c) */
+void orc_forcing_window(const double *modes, int n_modes, int nx, int ny, int nz, int ox, int oy, int oz, int wx,
+                        int wy, int wz, double *out);
 long orc_steps_done(const orc_state *s);
 int orc_threads(void);
 

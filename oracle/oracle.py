@@ -46,6 +46,8 @@ def lib():
         L.orc_get_f.argtypes = [C.c_void_p, dp]
         L.orc_set_f.argtypes = [C.c_void_p, dp]
         L.orc_get_uprev.argtypes = [C.c_void_p, dp]
+        L.orc_set_aext.argtypes = [C.c_void_p, dp]
+        L.orc_forcing_window.argtypes = [dp] + [C.c_int] * 10 + [dp]
         L.orc_steps_done.argtypes = [C.c_void_p]
         L.orc_steps_done.restype = C.c_long
         L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp]
@@ -149,6 +151,18 @@ def ac_update(phi, u, D, width):
     nz, ny, nx = phi.shape
     out = np.zeros(phi.shape)
     lib().orc_ac_update(nx, ny, nz, _p(phi), _p(u), float(D), float(width), _p(out))
+    return out
+
+
+def forcing_window(modes, box, origin, window):
+    """Body acceleration [3, wz, wy, wx] of the mode table on a box of shape `box`
+    (nz, ny, nx), on the window of shape `window` starting at `origin` (z, y, x)."""
+    modes = _f64(modes)
+    nz, ny, nx = box
+    oz, oy, ox = origin
+    wz, wy, wx = window
+    out = np.zeros((3, wz, wy, wx))
+    lib().orc_forcing_window(_p(modes), len(modes), nx, ny, nz, ox, oy, oz, wx, wy, wz, _p(out))
     return out
 
 
@@ -260,6 +274,12 @@ class Oracle:
     def set_f(self, f):
         f = _f64(f)
         lib().orc_set_f(self._h, _p(f))
+
+    def set_accel(self, a):
+        """Replace the body acceleration field ([3, nz, ny, nx])."""
+        self._aext = _f64(a)
+        assert self._aext.size == 3 * self.N
+        lib().orc_set_aext(self._h, _p(self._aext))
 
     def get_uprev(self):
         u = np.zeros((3,) + self.shape)

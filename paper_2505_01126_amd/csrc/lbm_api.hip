@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "lbm.h"
 #include "lbm_internal.h"
@@ -457,6 +459,315 @@ const char *lbm_last_error(const lbm_handle *h)
 {
     if (!h) return g_init_err.c_str();
     return h->err.c_str();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct lbm_batch {
+    std::vector<lbm_handle *> m;
+    std::vector<int> cur0;        // members' buffer parity when the tables were built
+    std::vector<lbm::Params> P;   // per-member parameters (the batch's own z-chunk)
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream the step-pair graph is recorded on
+    char *table = nullptr;
+    size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
+    int storage = 0, grid = 0, parity = 0, zchunk = 32;
+    bool tp = false, frc = false, ml = false, dirty = true;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+
+    int fail(int code, const std::string &msg)
+    {
+        err = msg;
+        return code;
+    }
+    int hip(hipError_t e, const char *what)
+    {
+        if (e == hipSuccess) return LBM_OK;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBM_EHIP;
+    }
+    lbm::Params *d_tab() { return (lbm::Params *)(table + off_tab); }
+    lbm::Buffers *d_buf() { return (lbm::Buffers *)(table + off_buf); }
+    uint32_t *d_first() { return (uint32_t *)(table + off_first); }
+    uint32_t *d_counter() { return (uint32_t *)(table + off_counter); }
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+};
+
+namespace {
+
+struct BatchOffsets {
+    size_t tab, buf, first, counter, total;
+};
+
+BatchOffsets batch_offsets(int n)
+{
+    BatchOffsets o{};
+    size_t off = 0;
+    o.tab = off;
+    off = align_up(off + sizeof(lbm::Params) * (size_t)n);
+    o.buf = off;
+    off = align_up(off + sizeof(lbm::Buffers) * 2 * (size_t)n);
+    o.first = off;
+    off = align_up(off + sizeof(uint32_t) * ((size_t)n + 1));
+    o.counter = off;
+    off = align_up(off + sizeof(uint32_t) * 2);
+    o.total = off;
+    return o;
+}
+
+void set_zchunk(lbm::Params &P, int zc)
+{
+    P.zchunk = zc > P.nz ? P.nz : zc;
+    P.gz = (P.nz + P.zchunk - 1) / P.zchunk;
+    P.nblocks = P.gx * P.gy * P.gz;
+}
+
+// Upload the parameter table, both parities of the buffer table and the
+// work-item prefix sums for the members' current state.
+int batch_upload(lbm_batch *b)
+{
+    const int n = (int)b->m.size();
+    std::vector<lbm::Buffers> buf(2 * (size_t)n);
+    std::vector<uint32_t> first((size_t)n + 1, 0u);
+    for (int i = 0; i < n; i++) {
+        lbm_handle *h = b->m[i];
+        b->cur0[i] = h->cur;
+        for (int p = 0; p < 2; p++) {
+            const int c = h->cur ^ p, o = c ^ 1;
+            buf[(size_t)p * n + i] = lbm::Buffers{h->f(c), h->f(o), h->phi(c), h->phi(o), h->u(c), h->u(o)};
+        }
+        first[i + 1] = first[i] + (uint32_t)b->P[i].nblocks;
+    }
+    // both queue counters start at zero (each launch clears the other one)
+    hipError_t e = hipMemsetAsync(b->d_counter(), 0, 2 * sizeof(uint32_t), b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tab(), b->P.data(), sizeof(lbm::Params) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_buf(), buf.data(), sizeof(lbm::Buffers) * 2 * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_first(), first.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // host staging is released below
+    if (e != hipSuccess) return b->hip(e, "batch table upload");
+    b->parity = 0;
+    b->dirty = false;
+    b->drop_graph();
+    return LBM_OK;
+}
+
+// one launch of the batch kernel with the given parity of the buffer table
+hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
+{
+    const int n = (int)b->m.size();
+    return lbm::launch_step_batch(b->d_tab(), b->d_buf() + (size_t)parity * n, b->d_first(), n, b->d_counter(),
+                                  parity, b->storage, b->tp, b->frc, b->ml, b->grid, s);
+}
+
+void batch_advance(lbm_batch *b, int64_t k)
+{
+    for (lbm_handle *h : b->m) {
+        h->cur ^= (int)(k & 1);
+        h->steps += k;
+    }
+    b->parity ^= (int)(k & 1);
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;  // member shapes and kernel flags -> z-chunk
+thread_local std::string g_batch_err;
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_bytes(int n)
+{
+    if (n < 1 || n > LBM_BATCH_MAX) return 0;
+    return batch_offsets(n).total;
+}
+
+int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d_table, size_t table_bytes)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    auto bad = [](int code, const char *why) {
+        g_batch_err = why;
+        return code;
+    };
+    if (n < 1 || n > LBM_BATCH_MAX || !members) return bad(LBM_EINVAL, "n must be in 1 .. LBM_BATCH_MAX");
+    if (!d_table || ((uintptr_t)d_table % ALIGN) != 0)
+        return bad(LBM_EINVAL, "table must be a 256-byte aligned device pointer");
+    const BatchOffsets o = batch_offsets(n);
+    if (table_bytes < o.total) return bad(LBM_ENOSPACE, "table smaller than lbm_batch_bytes(n)");
+    const lbm_handle *h0 = members[0];
+    if (!h0) return bad(LBM_EINVAL, "NULL member");
+    std::vector<lbm_handle *> m(members, members + n);
+    std::vector<lbm_handle *> sorted(m);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return bad(LBM_EINVAL, "repeated member");
+    for (lbm_handle *h : m) {
+        if (!h) return bad(LBM_EINVAL, "NULL member");
+        if (h->cfg.storage != h0->cfg.storage || h->cfg.two_phase != h0->cfg.two_phase ||
+            h->cfg.curv_mode != h0->cfg.curv_mode || (h->cfg.n_modes > 0) != (h0->cfg.n_modes > 0))
+            return bad(LBM_EINVAL, "members differ in storage, two_phase, curv_mode or forcing");
+        if (h->stream != h0->stream) return bad(LBM_EINVAL, "members are on different streams");
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return bad(LBM_EINVAL, "out of host memory");
+    b->m = m;
+    b->cur0.assign(n, 0);
+    b->stream = h0->stream;
+    b->table = (char *)d_table;
+    b->off_tab = o.tab;
+    b->off_buf = o.buf;
+    b->off_first = o.first;
+    b->off_counter = o.counter;
+    b->storage = h0->cfg.storage;
+    b->tp = h0->cfg.two_phase != 0;
+    b->frc = h0->cfg.n_modes > 0;
+    b->ml = h0->cfg.curv_mode == LBM_CURV_MLP;
+    for (lbm_handle *h : m) b->P.push_back(h->P);
+    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml);
+    if (b->grid <= 0) {
+        delete b;
+        return bad(LBM_EHIP, "occupancy query failed");
+    }
+    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return bad(LBM_EHIP, "capture stream creation failed");
+    }
+    if (int rc = batch_upload(b)) {
+        g_batch_err = b->err;
+        (void)hipStreamDestroy(b->capture);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    if (!b) return LBM_EINVAL;
+    if (nsteps < 0) return b->fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return LBM_OK;
+    const int n = (int)b->m.size();
+    for (int i = 0; i < n; i++) {
+        lbm_handle *h = b->m[i];
+        if (b->ml && !h->mlp_set) return b->fail(LBM_ESTATE, "MLP weights not set on a member");
+        if (h->cur != (b->cur0[i] ^ b->parity)) b->dirty = true;  // stepped on its own meanwhile
+    }
+    if (b->dirty)
+        if (int rc = batch_upload(b)) return rc;
+    int64_t left = nsteps;
+    if (b->parity == 1) {  // realign so that graph replays start at parity 0
+        if (int rc = b->hip(batch_launch(b, 1, b->stream), "batch kernel")) return rc;
+        batch_advance(b, 1);
+        left--;
+    }
+    if (left >= 2 && !b->exec) {
+        hipGraph_t g = nullptr;
+        // recorded on the private stream (the members' stream may be the
+        // legacy default stream, which cannot be captured), replayed on theirs
+        hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e0 = batch_launch(b, 0, b->capture);
+            hipError_t e1 = batch_launch(b, 1, b->capture);
+            e = hipStreamEndCapture(b->capture, &g);
+            if (e == hipSuccess) e = e0 != hipSuccess ? e0 : e1;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return b->hip(e, "batch graph capture");
+        }
+    }
+    for (; left >= 2; left -= 2) {
+        if (int rc = b->hip(hipGraphLaunch(b->exec, b->stream), "batch graph launch")) return rc;
+        batch_advance(b, 2);
+    }
+    if (left == 1) {
+        if (int rc = b->hip(batch_launch(b, 0, b->stream), "batch kernel")) return rc;
+        batch_advance(b, 1);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out)
+{
+    if (!b) return LBM_EINVAL;
+    if (steps_per_candidate < 1) return b->fail(LBM_EINVAL, "steps_per_candidate must be >= 1");
+    std::vector<std::string> shapes;
+    for (lbm_handle *h : b->m)
+        shapes.push_back(std::to_string(h->cfg.nx) + "x" + std::to_string(h->cfg.ny) + "x" + std::to_string(h->cfg.nz));
+    std::sort(shapes.begin(), shapes.end());
+    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d");
+    for (const std::string &sh : shapes) key += "," + sh;
+    auto apply = [&](int zc) {
+        for (lbm::Params &P : b->P) set_zchunk(P, zc);
+        b->zchunk = zc;
+        b->dirty = true;
+    };
+    int best = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) best = it->second;
+    }
+    if (best < 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (int rc = b->hip(hipEventCreate(&e0), "event")) return rc;
+        if (int rc = b->hip(hipEventCreate(&e1), "event")) {
+            (void)hipEventDestroy(e0);
+            return rc;
+        }
+        float best_ms = 0.f;
+        int rc = LBM_OK;
+        for (int zc : {8, 16, 32, 64}) {
+            apply(zc);
+            if ((rc = lbm_batch_step(b, 1))) break;
+            if ((rc = b->hip(hipEventRecord(e0, b->stream), "event"))) break;
+            if ((rc = lbm_batch_step(b, steps_per_candidate))) break;
+            if ((rc = b->hip(hipEventRecord(e1, b->stream), "event"))) break;
+            if ((rc = b->hip(hipEventSynchronize(e1), "event"))) break;
+            float ms = 0.f;
+            if ((rc = b->hip(hipEventElapsedTime(&ms, e0, e1), "event"))) break;
+            if (best < 0 || ms < best_ms) {
+                best = zc;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    apply(best);
+    if (zchunk_out) *zchunk_out = best;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch *b)
+{
+    if (b) {
+        b->drop_graph();
+        if (b->capture) (void)hipStreamDestroy(b->capture);
+    }
+    delete b;
+    return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b)
+{
+    if (!b) return g_batch_err.c_str();
+    return b->err.c_str();
 }
 
 }  // extern "C"

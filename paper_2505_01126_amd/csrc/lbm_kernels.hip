@@ -209,8 +209,11 @@ __device__ __forceinline__ void surface_fd(const PhiGrad &G, const Params &P, fl
 
 // Learned curvature: K_FD and |g| at the site, and whether the network is
 // consulted (interface cell 0.02 < phi < 0.98 with |K_FD| > k_lo).
+// (The learned-curvature helpers are contraction-free, so that every inlined
+// copy -- single-box and batch kernels -- rounds identically.)
 __device__ __forceinline__ bool mlp_select(const PhiGrad &G, const Params &P, float &kfd, float &gn)
 {
+#pragma clang fp contract(off)
     const float *g = G.g, *H = G.H;
     const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
     kfd = 0.f;
@@ -233,6 +236,7 @@ __device__ __forceinline__ bool mlp_select(const PhiGrad &G, const Params &P, fl
 __device__ __forceinline__ void surface_blend(const PhiGrad &G, const Params &P, float kfd, float gn,
                                               const float (&y)[4], float (&fs)[3])
 {
+#pragma clang fp contract(off)
     const float nn = sqrtf(y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
     if (!(isfinite(y[0]) && isfinite(nn) && nn >= 0.5f && nn <= 1.5f)) {
         surface_fd(G, P, fs);
@@ -493,8 +497,11 @@ __device__ __forceinline__ void lds_barrier()
 // Software pipeline over the z planes of a chunk: while plane z is processed,
 // the phi plane z+4, the face velocities of plane z+1, the 27 populations of
 // plane z+1 and the site's own phi and u_z ahead are already being fetched.
+// One work item: the xy tile and z chunk with linear index L (x tile fastest,
+// then y tile, then z chunk) of one box.  Every thread of the workgroup calls
+// it; it leaves no LDS state that the next call relies on.
 template <int S, bool TP, bool FRC, bool ML>
-__global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
+__device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L)
 {
     using T = typename Pop<S>::T;
     // Where the next plane's populations are fetched: 16-bit values pack two
@@ -507,12 +514,6 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t N = plane * (uint32_t)nz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    // Workgroups are handed to the 8 XCDs round-robin by launch index; give
-    // XCD j a contiguous run of tiles (x fastest, then y, then z chunk) so that
-    // neighbouring tiles share that XCD's L2 (halo rows, +-1 shifted rows).
-    const uint32_t H = blockIdx.x, q8 = (uint32_t)P.nblocks / 8u, r8 = (uint32_t)P.nblocks % 8u;
-    const uint32_t xcd = H % 8u, idx = H / 8u;
-    const uint32_t L = (xcd < r8 ? xcd * (q8 + 1u) : r8 * (q8 + 1u) + (xcd - r8) * q8) + idx;
     const int bx = (int)(L % (uint32_t)P.gx), by = (int)((L / (uint32_t)P.gx) % (uint32_t)P.gy);
     const int bz = (int)(L / ((uint32_t)P.gx * (uint32_t)P.gy));
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * P.zchunk;
@@ -809,6 +810,51 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
     }
 }
 
+// One box per launch.  Workgroups are handed to the 8 XCDs round-robin by
+// launch index; XCD j gets a contiguous run of tiles so that neighbouring
+// tiles share that XCD's L2 (halo rows, +-1 shifted rows).
+template <int S, bool TP, bool FRC, bool ML>
+__global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
+{
+    const uint32_t H = blockIdx.x, q8 = (uint32_t)P.nblocks / 8u, r8 = (uint32_t)P.nblocks % 8u;
+    const uint32_t xcd = H % 8u, idx = H / 8u;
+    const uint32_t L = (xcd < r8 ? xcd * (q8 + 1u) : r8 * (q8 + 1u) + (xcd - r8) * q8) + idx;
+    step_tile<S, TP, FRC, ML>(P, B, L);
+}
+
+// A batch of independent boxes in one launch: a persistent grid takes work
+// items (box, tile) from a queue; item k belongs to the box b with
+// first[b] <= k < first[b + 1].  The queue counter of this launch is
+// counter[parity]; the launch clears the other one for the next launch on the
+// stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
+template <int S, bool TP, bool FRC, bool ML>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(ML ? 1 : 3)))
+k_step_batch(const Params *__restrict__ tab,
+                                                         const Buffers *__restrict__ buf,
+                                                         const uint32_t *__restrict__ first, int nbox,
+                                                         uint32_t *counter, int parity)
+{
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    const uint32_t total = first[nbox];
+    if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[parity], 1u);
+        __syncthreads();
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();  // s_item read by all; the previous item's LDS traffic is over
+        if (item >= total) break;
+        int lo = 0, hi = nbox - 1;  // last box with first[b] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        step_tile<S, TP, FRC, ML>(tab[b], buf[b], item - first[b]);
+    }
+}
+
 // ----------------------------------------------------------- initial state
 // f^0 = f^eq(p*0, u0) + w H : A0 / (2 c_s^4), A0 = -c_s^2 tau (grad u0 + grad u0^T),
 // written pre-shifted (slot of x - c_i) so that the first pull yields f^0 at x.
@@ -1053,6 +1099,30 @@ hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream
     dim3 grid(p.nblocks), block(TX, TY, 1);
     const bool tp = p.two_phase != 0, frc = p.n_modes > 0, ml = p.curv_mode == 1;
 #define CALL(S_, TP_, F_, M_) hipLaunchKernelGGL((k_step<S_, TP_, F_, M_>), grid, block, 0, s, p, b);
+    LBM_DISPATCH(storage, tp, frc, ml, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+int batch_grid(int storage, bool tp, bool frc, bool ml)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+#define CALL(S_, TP_, F_, M_) \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_>, NTHREADS, 0);
+    LBM_DISPATCH(storage, tp, frc, ml, CALL);
+#undef CALL
+    return per_cu * cus;
+}
+
+hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
+                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int grid,
+                             hipStream_t s)
+{
+    dim3 g(grid), block(TX, TY, 1);
+#define CALL(S_, TP_, F_, M_) \
+    hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_>), g, block, 0, s, tab, buf, first, nbox, counter, parity);
     LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     return hipGetLastError();

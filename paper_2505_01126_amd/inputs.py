@@ -294,3 +294,33 @@ def random_u(shape, scale=0.01, seed=0):
     """Smooth-free white-noise velocity (for conservation and parity probes)."""
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.uniform(-scale, scale, size=(3,) + tuple(shape)))
+
+
+def bubble_box_ensemble(count=128, seed=0, edges=(32, 96), n_range=(1, 8), d_range=(6.0, 20.0),
+                        ratio_range=(1.0, 10.0), width=4.0):
+    """Seeded ensemble of independent bubble-in-box instances of uneven size.
+
+    Instance k: a cubic periodic box with edge drawn from the multiples of 8 in
+    `edges`, n_k bubbles (uniform in `n_range`) with diameters uniform in
+    `d_range`, and a density ratio uniform in `ratio_range`.  Where the bubbles
+    do not fit without overlap, the count is lowered until they do.  Returns a
+    list of dicts with keys shape, phi0, ratio, n_bubbles.
+    """
+    rng = np.random.default_rng(seed)
+    choices = np.arange(edges[0], edges[1] + 1, 8)
+    out = []
+    for k in range(count):
+        n = int(choices[rng.integers(0, len(choices))])
+        nb = int(rng.integers(n_range[0], n_range[1] + 1))
+        ratio = float(rng.uniform(*ratio_range))
+        sub = int(rng.integers(0, 2 ** 31))
+        while True:
+            try:
+                phi0, _, _ = bubble_pack((n, n, n), nb, d_range, width=width, seed=sub, max_tries=20000)
+                break
+            except RuntimeError:
+                nb -= 1
+                if nb == 0:
+                    raise
+        out.append({"shape": (n, n, n), "phi0": phi0, "ratio": ratio, "n_bubbles": nb})
+    return out

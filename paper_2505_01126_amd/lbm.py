@@ -63,7 +63,14 @@ SYMBOLS = {
     "lbm_set_mlp": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_harvest": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_void_p,
                               C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "lbm_batch_bytes": (C.c_size_t, [C.c_int]),
+    "lbm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_size_t]),
+    "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_batch_tune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
 }
+BATCH_MAX = 4096
 MLP_IN = 32
 
 
@@ -174,6 +181,39 @@ def lbm_harvest(h, centers, radii, d_x, d_y, cap):
     _check(load_library().lbm_harvest(h, c.ctypes.data_as(dp), r.ctypes.data_as(dp), len(r), d_x, d_y, int(cap),
                                       C.byref(n)), h, "lbm_harvest")
     return n.value
+
+
+def _check_batch(rc, b, what):
+    if rc != LBM_OK:
+        L = load_library()
+        raise LbmError(f"{what}: {L.lbm_strerror(rc).decode()} ({rc}): {L.lbm_batch_last_error(b).decode()}")
+
+
+def lbm_batch_bytes(n):
+    return load_library().lbm_batch_bytes(int(n))
+
+
+def lbm_batch_create(members, d_table, table_bytes):
+    """members: sequence of handles (c_void_p); returns the batch handle."""
+    arr = (C.c_void_p * len(members))(*[m.value if isinstance(m, C.c_void_p) else m for m in members])
+    b = C.c_void_p()
+    rc = load_library().lbm_batch_create(C.byref(b), arr, len(members), d_table, table_bytes)
+    _check_batch(rc, None, "lbm_batch_create")
+    return b
+
+
+def lbm_batch_step(b, nsteps):
+    _check_batch(load_library().lbm_batch_step(b, int(nsteps)), b, "lbm_batch_step")
+
+
+def lbm_batch_tune(b, steps_per_candidate):
+    zc = C.c_int(0)
+    _check_batch(load_library().lbm_batch_tune(b, int(steps_per_candidate), C.byref(zc)), b, "lbm_batch_tune")
+    return zc.value
+
+
+def lbm_batch_destroy(b):
+    load_library().lbm_batch_destroy(b)
 
 
 def _torch():
@@ -328,3 +368,36 @@ class Mlp:
 
     def weights_fp16(self):
         return self.w16.cpu().numpy().view(np.float16).astype(np.float64)
+
+
+class Batch:
+    """Independent Lattice objects advanced together by one persistent launch
+    per step (see lbm_batch_* in include/lbm.h).  The lattices must outlive it."""
+
+    def __init__(self, lattices):
+        torch = _torch()
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        nbytes = lbm_batch_bytes(n)
+        if nbytes == 0:
+            raise LbmError(f"a batch holds 1 .. {BATCH_MAX} lattices")
+        self.table = torch.empty(nbytes, dtype=torch.uint8, device=self.lattices[0].device)
+        self.b = lbm_batch_create([g.h for g in self.lattices], C.c_void_p(self.table.data_ptr()), nbytes)
+
+    def step(self, n=1):
+        lbm_batch_step(self.b, n)
+
+    def tune(self, steps_per_candidate=4):
+        """Pick the z-chunk length by timing; returns it (advances the lattices)."""
+        return lbm_batch_tune(self.b, steps_per_candidate)
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
