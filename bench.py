@@ -155,7 +155,7 @@ def batch_leg(steps, warmup, repeats, count=128, seed=3):
     per_instance(warmup)
     ms_single = timed(lambda: per_instance(steps))
     b = lbm.Batch(gs)
-    zc = b.tune(2)
+    tile, zc = b.tune(2)
     b.step(warmup)
     ms_batch = timed(lambda: b.step(steps))
     b.close()
@@ -163,7 +163,7 @@ def batch_leg(steps, warmup, repeats, count=128, seed=3):
         g.close()
     del gs
     torch.cuda.empty_cache()
-    return {"instances": count, "sites": sites, "storage": "f16", "curvature": "mlp", "zchunk": zc,
+    return {"instances": count, "sites": sites, "storage": "f16", "curvature": "mlp", "tile": tile, "zchunk": zc,
             "ms_per_step_batched": ms_batch, "ms_per_step_per_instance": ms_single,
             "mlups_batched": sites / (ms_batch * 1e-3) / 1e6, "mlups_per_instance": sites / (ms_single * 1e-3) / 1e6,
             "speedup": ms_single / ms_batch}
@@ -301,7 +301,7 @@ def main():
         line["batch"] = batch_leg(min(args.steps, 50), min(args.warmup, 10), args.repeats)
         bt = line["batch"]
         print(f"# batch: {bt['mlups_batched']:.0f} MLUPS batched vs {bt['mlups_per_instance']:.0f} per instance "
-              f"({bt['speedup']:.2f}x), z-chunk {bt['zchunk']}", file=sys.stderr, flush=True)
+              f"({bt['speedup']:.2f}x), tile {bt['tile']}, z-chunk {bt['zchunk']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -204,12 +204,19 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
  * MLP member has no weights. */
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
-/* Autotuner: time steps_per_candidate (>= 1) steps, after one warm-up step,
- * for each z-chunk length in {8, 16, 32, 64} and keep the fastest, cached per
- * set of member shapes for the life of the process (a cached set is not timed
- * again).  The timed steps advance the members like lbm_batch_step.  Waits for
- * the stream.  *zchunk_out (host, may be NULL) gets the chosen length. */
-int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out);
+/* Autotuner of the work decomposition: time steps_per_candidate (>= 1) steps,
+ * after one warm-up step, for each workgroup tile (64 x 4 or 32 x 8 sites:
+ * one or two x-rows per wave) and z-chunk length in {8, 16, 32, 64}, and keep
+ * the fastest, cached per set of member shapes for the life of the process (a
+ * cached set is not timed again).  The timed steps advance the members like
+ * lbm_batch_step; results do not depend on the decomposition.  Waits for the
+ * stream.  *tile_out and *zchunk_out (host, may be NULL) get the choice. */
+int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *tile_out, int *zchunk_out);
+
+/* Set the work decomposition by hand: tile 64 (64 x 4 sites) or 32 (32 x 8),
+ * z-chunk length >= 1 (clamped to each member's nz).  Takes effect at the next
+ * lbm_batch_step.  LBM_EINVAL for other values. */
+int lbm_batch_set_tiling(lbm_batch *b, int tile, int zchunk);
 
 /* Free the host-side batch (not the members, not d_table). */
 int lbm_batch_destroy(lbm_batch *b);

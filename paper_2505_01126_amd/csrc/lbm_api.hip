@@ -472,7 +472,7 @@ struct lbm_batch {
     hipStream_t capture = nullptr;  // private stream the step-pair graph is recorded on
     char *table = nullptr;
     size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
-    int storage = 0, grid = 0, parity = 0, zchunk = 32;
+    int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
     bool tp = false, frc = false, ml = false, dirty = true;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -521,8 +521,13 @@ BatchOffsets batch_offsets(int n)
     return o;
 }
 
-void set_zchunk(lbm::Params &P, int zc)
+// work decomposition of one box: tile width (64 or 32 sites in x, 256 sites
+// per tile) and z-chunk length
+void set_tiling(lbm::Params &P, int tile, int zc)
 {
+    const int ty = lbm::NTHREADS / tile;
+    P.gx = (P.nx + tile - 1) / tile;
+    P.gy = (P.ny + ty - 1) / ty;
     P.zchunk = zc > P.nz ? P.nz : zc;
     P.gz = (P.nz + P.zchunk - 1) / P.zchunk;
     P.nblocks = P.gx * P.gy * P.gz;
@@ -565,7 +570,7 @@ hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
 {
     const int n = (int)b->m.size();
     return lbm::launch_step_batch(b->d_tab(), b->d_buf() + (size_t)parity * n, b->d_first(), n, b->d_counter(),
-                                  parity, b->storage, b->tp, b->frc, b->ml, b->grid, s);
+                                  parity, b->storage, b->tp, b->frc, b->ml, b->tile, b->grid, s);
 }
 
 void batch_advance(lbm_batch *b, int64_t k)
@@ -578,7 +583,7 @@ void batch_advance(lbm_batch *b, int64_t k)
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;  // member shapes and kernel flags -> z-chunk
+std::map<std::string, std::pair<int, int>> g_tune_cache;  // member shapes and kernel flags -> (tile, z-chunk)
 thread_local std::string g_batch_err;
 
 }  // namespace
@@ -632,7 +637,7 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
     b->frc = h0->cfg.n_modes > 0;
     b->ml = h0->cfg.curv_mode == LBM_CURV_MLP;
     for (lbm_handle *h : m) b->P.push_back(h->P);
-    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml);
+    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->tile);
     if (b->grid <= 0) {
         delete b;
         return bad(LBM_EHIP, "occupancy query failed");
@@ -699,7 +704,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps)
     return LBM_OK;
 }
 
-int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out)
+int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *tile_out, int *zchunk_out)
 {
     if (!b) return LBM_EINVAL;
     if (steps_per_candidate < 1) return b->fail(LBM_EINVAL, "steps_per_candidate must be >= 1");
@@ -709,18 +714,17 @@ int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out)
     std::sort(shapes.begin(), shapes.end());
     std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d");
     for (const std::string &sh : shapes) key += "," + sh;
-    auto apply = [&](int zc) {
-        for (lbm::Params &P : b->P) set_zchunk(P, zc);
-        b->zchunk = zc;
-        b->dirty = true;
-    };
-    int best = -1;
+    auto apply = [&](int tile, int zc) -> int { return lbm_batch_set_tiling(b, tile, zc); };
+    int best_tile = -1, best_zc = -1;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) best = it->second;
+        if (it != g_tune_cache.end()) {
+            best_tile = it->second.first;
+            best_zc = it->second.second;
+        }
     }
-    if (best < 0) {
+    if (best_tile < 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (int rc = b->hip(hipEventCreate(&e0), "event")) return rc;
         if (int rc = b->hip(hipEventCreate(&e1), "event")) {
@@ -729,28 +733,48 @@ int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *zchunk_out)
         }
         float best_ms = 0.f;
         int rc = LBM_OK;
-        for (int zc : {8, 16, 32, 64}) {
-            apply(zc);
-            if ((rc = lbm_batch_step(b, 1))) break;
-            if ((rc = b->hip(hipEventRecord(e0, b->stream), "event"))) break;
-            if ((rc = lbm_batch_step(b, steps_per_candidate))) break;
-            if ((rc = b->hip(hipEventRecord(e1, b->stream), "event"))) break;
-            if ((rc = b->hip(hipEventSynchronize(e1), "event"))) break;
-            float ms = 0.f;
-            if ((rc = b->hip(hipEventElapsedTime(&ms, e0, e1), "event"))) break;
-            if (best < 0 || ms < best_ms) {
-                best = zc;
-                best_ms = ms;
+        for (int tile : {64, 32}) {
+            for (int zc : {8, 16, 32, 64}) {
+                if ((rc = apply(tile, zc))) break;
+                if ((rc = lbm_batch_step(b, 1))) break;
+                if ((rc = b->hip(hipEventRecord(e0, b->stream), "event"))) break;
+                if ((rc = lbm_batch_step(b, steps_per_candidate))) break;
+                if ((rc = b->hip(hipEventRecord(e1, b->stream), "event"))) break;
+                if ((rc = b->hip(hipEventSynchronize(e1), "event"))) break;
+                float ms = 0.f;
+                if ((rc = b->hip(hipEventElapsedTime(&ms, e0, e1), "event"))) break;
+                if (best_tile < 0 || ms < best_ms) {
+                    best_tile = tile;
+                    best_zc = zc;
+                    best_ms = ms;
+                }
             }
+            if (rc) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc) return rc;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = best;
+        g_tune_cache[key] = {best_tile, best_zc};
     }
-    apply(best);
-    if (zchunk_out) *zchunk_out = best;
+    if (int rc = apply(best_tile, best_zc)) return rc;
+    if (tile_out) *tile_out = best_tile;
+    if (zchunk_out) *zchunk_out = best_zc;
+    return LBM_OK;
+}
+
+int lbm_batch_set_tiling(lbm_batch *b, int tile, int zchunk)
+{
+    if (!b) return LBM_EINVAL;
+    if (tile != 64 && tile != 32) return b->fail(LBM_EINVAL, "tile must be 64 or 32");
+    if (zchunk < 1) return b->fail(LBM_EINVAL, "zchunk must be >= 1");
+    const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, tile);
+    if (grid <= 0) return b->fail(LBM_EHIP, "occupancy query failed");
+    for (lbm::Params &P : b->P) set_tiling(P, tile, zchunk);
+    b->tile = tile;
+    b->zchunk = zchunk;
+    b->grid = grid;
+    b->dirty = true;
     return LBM_OK;
 }
 

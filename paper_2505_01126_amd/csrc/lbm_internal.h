@@ -56,10 +56,11 @@ hipError_t launch_init(const Params &p, int storage, void *fout, double *phi_out
                        const double *u0, const double *ps0, hipStream_t s);
 hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream_t s);
 // batch of boxes in one persistent launch (see k_step_batch)
-int batch_grid(int storage, bool tp, bool frc, bool ml);
+// tile: workgroup tile width in x, 64 (64 x 4 sites) or 32 (32 x 8)
+int batch_grid(int storage, bool tp, bool frc, bool ml, int tile);
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
-                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int grid,
-                             hipStream_t s);
+                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int tile,
+                             int grid, hipStream_t s);
 hipError_t launch_moments(const Params &p, int storage, const void *fin, const double *phi, float *rho, float *pr,
                           float *u, double *phi_out, hipStream_t s);
 constexpr int HARVEST_BLOCKS = 1024;

@@ -470,17 +470,24 @@ __device__ __forceinline__ void forcing_at(const Params &P, float4 ex, uint32_t 
 
 // ------------------------------------------------------------ fused step
 constexpr int HX = 3, HY = 3;                  // phi tile halo (WENO-5 needs 3)
-constexpr int PX = TX + 2 * HX, PY = TY + 2 * HY;
-constexpr int PLANE = PX * PY;                 // phi values per staged plane
-constexpr int QX = TX + 2, QY = TY + 2;        // Q tile (halo 1)
-constexpr int QPLANE = QX * QY;
 constexpr int NRING = 7;                       // phi planes z-3 .. z+3
-constexpr int LOADS = (PLANE + NTHREADS - 1) / NTHREADS;
-constexpr int QPTS = (QPLANE + NTHREADS - 1) / NTHREADS;
-constexpr int NXF = TY * (TX + 1);             // x faces of a plane tile (left of each site + 1)
-constexpr int NYF = (TY + 1) * TX;             // y faces
-constexpr int NFACE = NXF + NYF;
-constexpr int FROUNDS = (NFACE + NTHREADS - 1) / NTHREADS;
+
+// Workgroup tile of TW x (256 / TW) sites: TW = 64 is one wave per x-row (the
+// single-box kernel); TW = 32 puts two rows in a wave (boxes of 32 or 96 sites
+// in x waste no lanes).  LDS tiles and per-thread work rounds derive from it.
+template <int TW> struct Tile {
+    static constexpr int X = TW, Y = NTHREADS / TW;
+    static constexpr int PX = X + 2 * HX, PY = Y + 2 * HY;
+    static constexpr int PLANE = PX * PY;         // phi values per staged plane
+    static constexpr int QX = X + 2, QY = Y + 2;  // Q tile (halo 1)
+    static constexpr int QPLANE = QX * QY;
+    static constexpr int LOADS = (PLANE + NTHREADS - 1) / NTHREADS;
+    static constexpr int QPTS = (QPLANE + NTHREADS - 1) / NTHREADS;
+    static constexpr int NXF = Y * (X + 1);       // x faces of a plane tile (left of each site + 1)
+    static constexpr int NYF = (Y + 1) * X;       // y faces
+    static constexpr int NFACE = NXF + NYF;
+    static constexpr int FROUNDS = (NFACE + NTHREADS - 1) / NTHREADS;
+};
 
 __device__ __forceinline__ int ring(int z) { return (z + 4 * NRING) % NRING; }
 
@@ -500,10 +507,14 @@ __device__ __forceinline__ void lds_barrier()
 // One work item: the xy tile and z chunk with linear index L (x tile fastest,
 // then y tile, then z chunk) of one box.  Every thread of the workgroup calls
 // it; it leaves no LDS state that the next call relies on.
-template <int S, bool TP, bool FRC, bool ML>
+template <int S, bool TP, bool FRC, bool ML, int TW = TX>
 __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L)
 {
     using T = typename Pop<S>::T;
+    using TL = Tile<TW>;
+    constexpr int TXW = TL::X, TYW = TL::Y, PX = TL::PX, PLANE = TL::PLANE, QX = TL::QX, QPLANE = TL::QPLANE,
+                  LOADS = TL::LOADS, QPTS = TL::QPTS, NXF = TL::NXF, NYF = TL::NYF, NFACE = TL::NFACE,
+                  FROUNDS = TL::FROUNDS;
     // Where the next plane's populations are fetched: 16-bit values pack two
     // to a register, so FP16/BF16 fetch right after the moments (longest
     // prefetch distance) and still fit three waves per SIMD; FP32 fetches after
@@ -513,10 +524,10 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t N = plane * (uint32_t)nz;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TXW + tx;
     const int bx = (int)(L % (uint32_t)P.gx), by = (int)((L / (uint32_t)P.gx) % (uint32_t)P.gy);
     const int bz = (int)(L / ((uint32_t)P.gx * (uint32_t)P.gy));
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * P.zchunk;
+    const int x0 = bx * TXW, y0 = by * TYW, z0 = bz * P.zchunk;
     const int zend = min(z0 + P.zchunk, nz);
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
@@ -526,7 +537,8 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const float *__restrict__ uy_in = B.uin + N;
     const float *__restrict__ uz_in = B.uin + 2 * (size_t)N;
 
-    const int yw = __builtin_amdgcn_readfirstlane(yg);
+    // with one x-row per wave the row is wave-uniform (scalar forcing loads)
+    const int yw = TW == 64 ? __builtin_amdgcn_readfirstlane(yg) : yg;
     uint32_t src_xy[9];
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
@@ -562,7 +574,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     __shared__ float sjy[TP ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
     // learned curvature: weights and per-wave scratch
-    __shared__ char mlp_raw[ML ? sizeof(MlpW) + TY * sizeof(MlpWave) : 1];
+    __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
     MlpW &smw = *(MlpW *)mlp_raw;
     MlpWave *smwave = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
     if constexpr (ML) load_weights((const uint16_t *)P.mlp, smw, tid, NTHREADS);
@@ -627,7 +639,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     };
     // advective x and y fluxes of plane z through the faces of the tile, each
     // face once: x face f of row r lies between tile columns f-1 and f
-    // (f = 0..TX), y face r of column x between tile rows r-1 and r (r = 0..TY)
+    // (f = 0..TXW), y face r of column x between tile rows r-1 and r (r = 0..TYW)
     auto compute_faces = [&](int z) {
         const float *pl = sphi[ring(z)];
 #pragma unroll
@@ -662,12 +674,12 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         for (int k = 0; k < FROUNDS; k++) {
             const int t = tid + k * NTHREADS;
             if (t < NXF) {
-                const int r = t / (TX + 1), f = t - r * (TX + 1);
+                const int r = t / (TXW + 1), f = t - r * (TXW + 1);
                 f_c[k] = (r + HY) * PX + (f - 1 + HX);
                 f_isx[k] = true;
             } else {
                 const int t2 = t - NXF;
-                const int r = t2 / TX, xx = t2 - r * TX;
+                const int r = t2 / TXW, xx = t2 - r * TXW;
                 f_c[k] = (r - 1 + HY) * PX + (xx + HX);
                 f_isx[k] = false;
             }
@@ -723,8 +735,8 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
                 // four independent FP64 partial sums keep the dependent add chains short
                 double acc[4];
-                acc[0] = (double)sjx[ty * (TX + 1) + tx] - (double)sjx[ty * (TX + 1) + tx + 1];
-                acc[0] += (double)sjy[ty * TX + tx] - (double)sjy[(ty + 1) * TX + tx];
+                acc[0] = (double)sjx[ty * (TXW + 1) + tx] - (double)sjx[ty * (TXW + 1) + tx + 1];
+                acc[0] += (double)sjy[ty * TXW + tx] - (double)sjy[(ty + 1) * TXW + tx];
                 {
                     float v[6];
 #pragma unroll
@@ -778,7 +790,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         float fs[3] = {0.f, 0.f, 0.f};
         if constexpr (ML) {
             float y[4] = {0.f, 0.f, 0.f, 0.f};
-            mlp_wave(smw, smwave[ty], sel, ph, y, tx);
+            mlp_wave(smw, smwave[tid >> 6], sel, ph, y, tid & 63);
             if (active) {
                 if (sel) surface_blend(G, P, kfd, gn, y, fs);
                 else surface_fd(G, P, fs);
@@ -827,15 +839,13 @@ __global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
 // first[b] <= k < first[b + 1].  The queue counter of this launch is
 // counter[parity]; the launch clears the other one for the next launch on the
 // stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
-template <int S, bool TP, bool FRC, bool ML>
+template <int S, bool TP, bool FRC, bool ML, int TW>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(ML ? 1 : 3)))
-k_step_batch(const Params *__restrict__ tab,
-                                                         const Buffers *__restrict__ buf,
-                                                         const uint32_t *__restrict__ first, int nbox,
-                                                         uint32_t *counter, int parity)
+k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+             int nbox, uint32_t *counter, int parity)
 {
     __shared__ uint32_t s_item;
-    const int tid = threadIdx.y * TX + threadIdx.x;
+    const int tid = threadIdx.y * TW + threadIdx.x;
     const uint32_t total = first[nbox];
     if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
     for (;;) {
@@ -851,7 +861,7 @@ k_step_batch(const Params *__restrict__ tab,
             else hi = mid - 1;
         }
         const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<S, TP, FRC, ML>(tab[b], buf[b], item - first[b]);
+        step_tile<S, TP, FRC, ML, TW>(tab[b], buf[b], item - first[b]);
     }
 }
 
@@ -1104,25 +1114,39 @@ hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream
     return hipGetLastError();
 }
 
-int batch_grid(int storage, bool tp, bool frc, bool ml)
+int batch_grid(int storage, bool tp, bool frc, bool ml, int tile)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-#define CALL(S_, TP_, F_, M_) \
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_>, NTHREADS, 0);
+#define CALL(S_, TP_, F_, M_)                                                                              \
+    {                                                                                                      \
+        if (tile == 32)                                                                                    \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 32>,  \
+                                                               NTHREADS, 0);                               \
+        else                                                                                               \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 64>,  \
+                                                               NTHREADS, 0);                               \
+    }
     LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     return per_cu * cus;
 }
 
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
-                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int grid,
-                             hipStream_t s)
+                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int tile,
+                             int grid, hipStream_t s)
 {
-    dim3 g(grid), block(TX, TY, 1);
-#define CALL(S_, TP_, F_, M_) \
-    hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_>), g, block, 0, s, tab, buf, first, nbox, counter, parity);
+    dim3 g(grid), block(tile, NTHREADS / tile, 1);
+#define CALL(S_, TP_, F_, M_)                                                                              \
+    {                                                                                                      \
+        if (tile == 32)                                                                                    \
+            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 32>), g, block, 0, s, tab, buf, first, nbox,  \
+                               counter, parity);                                                           \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 64>), g, block, 0, s, tab, buf, first, nbox,  \
+                               counter, parity);                                                           \
+    }
     LBM_DISPATCH(storage, tp, frc, ml, CALL);
 #undef CALL
     return hipGetLastError();

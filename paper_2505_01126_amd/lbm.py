@@ -66,7 +66,8 @@ SYMBOLS = {
     "lbm_batch_bytes": (C.c_size_t, [C.c_int]),
     "lbm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_size_t]),
     "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
-    "lbm_batch_tune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "lbm_batch_tune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "lbm_batch_set_tiling": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
     "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -207,9 +208,16 @@ def lbm_batch_step(b, nsteps):
 
 
 def lbm_batch_tune(b, steps_per_candidate):
+    """Returns (tile width, z-chunk length)."""
+    tile = C.c_int(0)
     zc = C.c_int(0)
-    _check_batch(load_library().lbm_batch_tune(b, int(steps_per_candidate), C.byref(zc)), b, "lbm_batch_tune")
-    return zc.value
+    _check_batch(load_library().lbm_batch_tune(b, int(steps_per_candidate), C.byref(tile), C.byref(zc)), b,
+                 "lbm_batch_tune")
+    return tile.value, zc.value
+
+
+def lbm_batch_set_tiling(b, tile, zchunk):
+    _check_batch(load_library().lbm_batch_set_tiling(b, int(tile), int(zchunk)), b, "lbm_batch_set_tiling")
 
 
 def lbm_batch_destroy(b):
@@ -388,8 +396,13 @@ class Batch:
         lbm_batch_step(self.b, n)
 
     def tune(self, steps_per_candidate=4):
-        """Pick the z-chunk length by timing; returns it (advances the lattices)."""
+        """Pick the tile width and z-chunk length by timing; returns (tile, zchunk)
+        (the timed steps advance the lattices)."""
         return lbm_batch_tune(self.b, steps_per_candidate)
+
+    def set_tiling(self, tile, zchunk):
+        """Work decomposition by hand: tile width 64 or 32, z-chunk length."""
+        lbm_batch_set_tiling(self.b, tile, zchunk)
 
     def close(self):
         if getattr(self, "b", None) is not None:

@@ -68,8 +68,10 @@ def _assert_same(a, b, what):
         assert torch.equal(a[k], b[k]), f"{what}: field {k} differs"
 
 
-@pytest.mark.parametrize("storage,curv", [("f16", "fd"), ("f16", "mlp"), ("f32", "fd")])
-def test_batch_bit_identical_to_single_boxes(storage, curv):
+@pytest.mark.parametrize("storage,curv,tiling", [("f16", "fd", None), ("f16", "mlp", None), ("f32", "fd", None),
+                                                 ("f16", "fd", (32, 8)), ("f16", "mlp", (32, 16)),
+                                                 ("f32", "fd", (32, 64))])
+def test_batch_bit_identical_to_single_boxes(storage, curv, tiling):
     from paper_2505_01126_amd import lbm
 
     boxes = _boxes(storage, curv)
@@ -80,6 +82,8 @@ def test_batch_bit_identical_to_single_boxes(storage, curv):
     ref = [_fields(g) for g in alone]
     members = _make(boxes, w16)
     b = lbm.Batch(members)
+    if tiling is not None:
+        b.set_tiling(*tiling)  # 32 x 8 tiles: two x-rows per wave
     b.step(3)  # one graph replay (2 steps) + one single launch
     b.step(4)  # realign launch, one replay, tail launch
     for i, g in enumerate(members):
@@ -98,17 +102,17 @@ def test_batch_member_stepped_alone_and_tuned():
     b.step(2)
     members[1].step(1)  # on its own: the batch must pick up the new state
     b.step(2)
-    zc = b.tune(2)  # 4 candidates x (1 + 2) steps
-    assert zc in (8, 16, 32, 64)
-    assert b.tune(2) == zc  # cached: no further steps
+    tile, zc = b.tune(2)  # 8 candidates x (1 + 2) steps, every tile width and z-chunk
+    assert tile in (64, 32) and zc in (8, 16, 32, 64)
+    assert b.tune(2) == (tile, zc)  # cached: no further steps
     b.step(3)
-    total = [2 + 2 + 12 + 3] * len(boxes)
+    total = [2 + 2 + 24 + 3] * len(boxes)
     total[1] += 1
     for i, g in enumerate(members):
         assert g.steps == total[i]
         alone[i].step(total[i])
         _assert_same(_fields(g), _fields(alone[i]), f"box {i}")
-    print(f"autotuned z-chunk {zc}")
+    print(f"autotuned tile {tile}, z-chunk {zc}")
     b.close()
 
 
@@ -144,3 +148,7 @@ def test_batch_rejects_mixed_members():
         lbm.Batch([a, a])
     with pytest.raises(lbm.LbmError):
         lbm.Batch([])
+    b = lbm.Batch([a])
+    with pytest.raises(lbm.LbmError):
+        b.set_tiling(48, 8)
+    b.close()
