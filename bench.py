@@ -169,6 +169,44 @@ def batch_leg(steps, warmup, repeats, count=128, seed=3):
             "speedup": ms_single / ms_batch}
 
 
+def oracle_timing():
+    """The FP64 oracle on the host cores for the four workloads (BASELINE
+    configs 1-4): TGV 32^3 (200 steps), static droplet 64^3 (R = 12, ratio 10;
+    the first 500 of its 5000 steps), single-phase forced HIT 256^3 (20 steps),
+    512^3 bubbly HIT (2 steps).  Prints one line per workload as it finishes
+    and returns MLUPS per workload."""
+    import oracle as O
+    from paper_2505_01126_amd import inputs as I
+
+    out = {}
+
+    def run(name, o, steps, chunk):
+        o.step(1)
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            o.step(k)
+            done += k
+            print(f"# oracle {name}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+        dt = time.perf_counter() - t0
+        out[name] = {"mlups": o.N * steps / dt / 1e6, "steps": steps, "seconds": dt}
+
+    u, p, _ = I.tgv((32, 32, 32), 0.02)
+    run("tgv_32", O.Oracle((32, 32, 32), 0.8, u0=u, pstar0=p), 200, 100)
+    phi0, _ = I.droplet((64, 64, 64), 12.0, 4.0, seed=1)
+    run("droplet_64", O.Oracle((64, 64, 64), 1.0, phi0=phi0, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05,
+                               width=4.0, p0=0.0), 500, 100)
+    shape = (256, 256, 256)
+    u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=1)
+    run("hit_256", O.Oracle(shape, 0.55, u0=u0, modes=I.forcing_modes(1e-5, seed=2)), 20, 2)
+    del u0
+    shape, phi0, u0, params, nb = workload(512)
+    run("bubbly_hit_512", O.Oracle(shape, 0.515, phi0=phi0, u0=u0, **params), 2, 1)
+    return {"cores": O.threads(), "nproc": os.cpu_count(), "workloads": out}
+
+
 def copy_gbs(mib=1024, reps=10):
     """Device-to-device copy bandwidth (read + write bytes) on this GPU."""
     import torch
@@ -205,7 +243,14 @@ def cpu_baseline(seconds=15.0):
         steps += 2
     dt = time.perf_counter() - t0
     N = shape[0] * shape[1] * shape[2]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
             "sample": f"64^3 box of the same recipe ({nb} bubble of d=16, same parameters and forcing), "
                       f"{steps} steps in {dt:.1f} s"}
 
@@ -223,6 +268,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-box ensemble leg")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle on the four workloads (several minutes of CPU) and exit")
     ap.add_argument("--bandwidth-probe", action="store_true",
                     help="only run the streaming-kernel bandwidth probe (copy, read, write, 27-row) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -232,6 +279,16 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the z-slab multi-GPU layout is described in the design notes but not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_timing:
+        res = oracle_timing()
+        try:
+            with open("/proc/cpuinfo") as f:
+                res["cpu_model"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        print(json.dumps(res), flush=True)
+        return
 
     if args.bandwidth_probe:
         import subprocess

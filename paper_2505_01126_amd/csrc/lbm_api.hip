@@ -27,7 +27,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], frow, fx, partials, red, mlp, sph, hcount, total;
+    size_t f[2], phi[2], u[2], frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -61,6 +61,7 @@ Layout layout_of(const lbm_config &c)
     L.mlp = take(sizeof(uint16_t) * LBM_MLP_NPARAM);
     L.sph = take(sizeof(double) * 4 * lbm::MAX_SPHERES);
     L.hcount = take(sizeof(long long) * 2 * lbm::HARVEST_BLOCKS);
+    L.self_batch = take(lbm_batch_bytes(1));  // tables of the box's own one-member batch
     L.total = off;
     return L;
 }
@@ -109,6 +110,41 @@ const char *validate(const lbm_config *c)
 
 }  // namespace
 
+struct lbm_batch {
+    std::vector<lbm_handle *> m;
+    std::vector<int> cur0;        // members' buffer parity when the tables were built
+    std::vector<lbm::Params> P;   // per-member parameters (the batch's own z-chunk)
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream the step-pair graph is recorded on
+    char *table = nullptr;
+    size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
+    int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
+    bool tp = false, frc = false, ml = false, dirty = true;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+
+    int fail(int code, const std::string &msg)
+    {
+        err = msg;
+        return code;
+    }
+    int hip(hipError_t e, const char *what)
+    {
+        if (e == hipSuccess) return LBM_OK;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBM_EHIP;
+    }
+    lbm::Params *d_tab() { return (lbm::Params *)(table + off_tab); }
+    lbm::Buffers *d_buf() { return (lbm::Buffers *)(table + off_buf); }
+    uint32_t *d_first() { return (uint32_t *)(table + off_first); }
+    uint32_t *d_counter() { return (uint32_t *)(table + off_counter); }
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+};
+
 struct lbm_handle {
     lbm_config cfg{};
     lbm::Params P{};
@@ -118,6 +154,7 @@ struct lbm_handle {
     int cur = 0;
     int64_t steps = 0;
     bool mlp_set = false;
+    lbm_batch *self = nullptr;  // lbm_step runs the box as a one-member batch
     std::vector<float> frow_host, fx_host;
     std::string err;
 
@@ -292,6 +329,11 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
         delete h;
         return LBM_EHIP;
     }
+    if (lbm_batch_create(&h->self, &h, 1, h->ws + L.self_batch, lbm_batch_bytes(1)) != LBM_OK) {
+        g_init_err = std::string("step tables: ") + lbm_batch_last_error(nullptr);
+        delete h;
+        return LBM_EHIP;
+    }
     *out = h;
     return LBM_OK;
 }
@@ -301,15 +343,10 @@ int lbm_step(lbm_handle *h, int64_t nsteps)
     if (!h) return LBM_EINVAL;
     if (nsteps < 0) return h->fail(LBM_EINVAL, "nsteps must be >= 0");
     if (h->cfg.curv_mode == LBM_CURV_MLP && !h->mlp_set) return h->fail(LBM_ESTATE, "MLP weights not set");
-    for (int64_t n = 0; n < nsteps; n++) {
-        const int c = h->cur, o = 1 - c;
-        lbm::Buffers b{h->f(c), h->f(o), h->phi(c), h->phi(o), h->u(c), h->u(o)};
-        hipError_t e = lbm::launch_step(h->P, h->cfg.storage, b, h->stream);
-        if (e != hipSuccess) return h->hip(e, "step kernel");
-        h->cur = o;
-        h->steps++;
-    }
-    return LBM_OK;
+    h->self->stream = h->stream;
+    const int rc = lbm_batch_step(h->self, nsteps);
+    if (rc != LBM_OK) h->err = h->self->err;
+    return rc;
 }
 
 int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_phi)
@@ -439,6 +476,7 @@ int lbm_set_stream(lbm_handle *h, void *stream)
 
 int lbm_destroy(lbm_handle *h)
 {
+    if (h) lbm_batch_destroy(h->self);
     delete h;
     return LBM_OK;
 }
@@ -464,40 +502,6 @@ const char *lbm_last_error(const lbm_handle *h)
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
-struct lbm_batch {
-    std::vector<lbm_handle *> m;
-    std::vector<int> cur0;        // members' buffer parity when the tables were built
-    std::vector<lbm::Params> P;   // per-member parameters (the batch's own z-chunk)
-    hipStream_t stream = nullptr;
-    hipStream_t capture = nullptr;  // private stream the step-pair graph is recorded on
-    char *table = nullptr;
-    size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
-    int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
-    bool tp = false, frc = false, ml = false, dirty = true;
-    hipGraphExec_t exec = nullptr;
-    std::string err;
-
-    int fail(int code, const std::string &msg)
-    {
-        err = msg;
-        return code;
-    }
-    int hip(hipError_t e, const char *what)
-    {
-        if (e == hipSuccess) return LBM_OK;
-        err = std::string(what) + ": " + hipGetErrorString(e);
-        return LBM_EHIP;
-    }
-    lbm::Params *d_tab() { return (lbm::Params *)(table + off_tab); }
-    lbm::Buffers *d_buf() { return (lbm::Buffers *)(table + off_buf); }
-    uint32_t *d_first() { return (uint32_t *)(table + off_first); }
-    uint32_t *d_counter() { return (uint32_t *)(table + off_counter); }
-    void drop_graph()
-    {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        exec = nullptr;
-    }
-};
 
 namespace {
 

@@ -54,8 +54,7 @@ struct Buffers {
 
 hipError_t launch_init(const Params &p, int storage, void *fout, double *phi_out, float *u_out, const double *phi0,
                        const double *u0, const double *ps0, hipStream_t s);
-hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream_t s);
-// batch of boxes in one persistent launch (see k_step_batch)
+// the time step of one or many boxes in one persistent launch (see k_step_batch)
 // tile: workgroup tile width in x, 64 (64 x 4 sites) or 32 (32 x 8)
 int batch_grid(int storage, bool tp, bool frc, bool ml, int tile);
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,

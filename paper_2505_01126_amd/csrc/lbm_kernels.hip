@@ -88,6 +88,18 @@ template <class T> __device__ __forceinline__ void stb(void *base, uint32_t byte
     *(T *)((char *)base + byte_off) = v;
 }
 
+// Pointers into global memory.  Kernel arguments are known to be global; a
+// pointer read from a descriptor table (the batch kernel) is generic, and
+// generic (flat) accesses also count against the LDS wait counter, so every
+// LDS wait would then wait for the prefetches too.  These casts restore global
+// addressing.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ const LBM_GLOBAL T *gconst(const T *p)
+{
+    return (const LBM_GLOBAL T *)p;
+}
+template <class T> __device__ __forceinline__ LBM_GLOBAL T *gmut(T *p) { return (LBM_GLOBAL T *)p; }
+
 // Raw buffer access to one z plane of populations (27 rows of nx * ny): the
 // row offset i * plane goes in the scalar offset, the in-plane offset in the
 // vector offset, so no per-row vector address arithmetic is needed.
@@ -462,7 +474,7 @@ __device__ __forceinline__ void q_of(const float (&v)[27], float (&q)[3])
 // coefficients with the x twiddles ex = (cos t, sin t, cos 2t, sin 2t).
 __device__ __forceinline__ void forcing_at(const Params &P, float4 ex, uint32_t row, float (&a)[3])
 {
-    const float *r = P.frow + (size_t)row * FROW;
+    const LBM_GLOBAL float *r = gconst(P.frow) + (size_t)row * FROW;
 #pragma unroll
     for (int d = 0; d < 3; d++)
         a[d] = r[d] + (r[3 + d] * ex.x + r[6 + d] * ex.y) + (r[9 + d] * ex.z + r[12 + d] * ex.w);
@@ -507,7 +519,7 @@ __device__ __forceinline__ void lds_barrier()
 // One work item: the xy tile and z chunk with linear index L (x tile fastest,
 // then y tile, then z chunk) of one box.  Every thread of the workgroup calls
 // it; it leaves no LDS state that the next call relies on.
-template <int S, bool TP, bool FRC, bool ML, int TW = TX>
+template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0)>
 __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L)
 {
     using T = typename Pop<S>::T;
@@ -518,8 +530,10 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // Where the next plane's populations are fetched: 16-bit values pack two
     // to a register, so FP16/BF16 fetch right after the moments (longest
     // prefetch distance) and still fit three waves per SIMD; FP32 fetches after
-    // the phase-field work, the shorter live range that fits three waves.
-    constexpr bool kLatePrefetch = TP && S == 0;
+    // the phase-field work, the shorter live range that fits three waves.  The
+    // batch kernel, which holds a few more registers for its work queue, fetches
+    // late in every storage mode (a spilled prefetch register would stall).
+    constexpr bool kLatePrefetch = TP && LATE_PF;
     constexpr uint32_t ES = sizeof(T);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
@@ -533,9 +547,12 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const T *__restrict__ fin = (const T *)B.fin;
     T *__restrict__ fout = (T *)B.fout;
-    const float *__restrict__ ux_in = B.uin;
-    const float *__restrict__ uy_in = B.uin + N;
-    const float *__restrict__ uz_in = B.uin + 2 * (size_t)N;
+    const LBM_GLOBAL float *__restrict__ ux_in = gconst(B.uin);
+    const LBM_GLOBAL float *__restrict__ uy_in = ux_in + N;
+    const LBM_GLOBAL float *__restrict__ uz_in = ux_in + 2 * (size_t)N;
+    const LBM_GLOBAL double *__restrict__ phin = gconst(B.phin);
+    LBM_GLOBAL double *__restrict__ phout = gmut(B.phout);
+    LBM_GLOBAL float *__restrict__ uout = gmut(B.uout);
 
     // with one x-row per wave the row is wave-uniform (scalar forcing loads)
     const int yw = TW == 64 ? __builtin_amdgcn_readfirstlane(yg) : yg;
@@ -548,7 +565,10 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const uint32_t own_xy = (uint32_t)yg * nx + xg;
 
     float4 ex = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (FRC) ex = P.fx[xg];
+    if constexpr (FRC) {
+        const LBM_GLOBAL float *fx = gconst((const float *)P.fx) + 4 * xg;
+        ex = make_float4(fx[0], fx[1], fx[2], fx[3]);
+    }
     const uint32_t yrow = (uint32_t)yw;
 
     // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
@@ -561,9 +581,15 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         const __amdgpu_buffer_rsrc_t zsrc[3] = {plane_rsrc(fin + (size_t)wrapi(z + 1, nz) * pstride, pbytes),
                                                 plane_rsrc(fin + (size_t)z * pstride, pbytes),
                                                 plane_rsrc(fin + (size_t)wrapi(z - 1, nz) * pstride, pbytes)};
+        // running row offset, kept opaque so that the 27 offsets are not all
+        // precomputed into scalar registers
+        uint32_t soff = 0;
 #pragma unroll
-        for (int i = 0; i < 27; i++)
-            hv[i] = bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, i * plane * ES);
+        for (int i = 0; i < 27; i++) {
+            hv[i] = bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, soff);
+            soff += plane * ES;
+            asm volatile("" : "+s"(soff));
+        }
     };
 
     // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
@@ -577,7 +603,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
     MlpW &smw = *(MlpW *)mlp_raw;
     MlpWave *smwave = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
-    if constexpr (ML) load_weights((const uint16_t *)P.mlp, smw, tid, NTHREADS);
+    if constexpr (ML) load_weights(gconst((const uint16_t *)P.mlp), smw, tid, NTHREADS);
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
     bool f_isx[FROUNDS];
@@ -587,7 +613,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     double po = 0.0;        // prefetched own phi
 
     auto fetch_plane = [&](int z) {
-        const double *src = B.phin + (size_t)modi(z, nz) * plane;
+        const LBM_GLOBAL double *src = phin + (size_t)modi(z, nz) * plane;
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
@@ -609,7 +635,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             const int t = tid + k * NTHREADS;
             if (t < NFACE) {
                 const int c = f_c[k], st = f_isx[k] ? 1 : PX;
-                const float *ub = f_isx[k] ? ux_in : uy_in;
+                const LBM_GLOBAL float *ub = f_isx[k] ? ux_in : uy_in;
                 f_ul[k] = ub[zo + sxy[c]];
                 f_ur[k] = ub[zo + sxy[c + st]];
             }
@@ -697,7 +723,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         const float um = uz_in[(uint32_t)modi(z0 - 1, nz) * plane + own_xy];
         uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
         uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
-        po = B.phin[(size_t)z0 * plane + own_xy];
+        po = phin[(size_t)z0 * plane + own_xy];
         float v[6];
 #pragma unroll
         for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
@@ -780,8 +806,8 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
                 }
-                B.phout[(size_t)own] = po + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
-                if (more) po = B.phin[(size_t)own + plane];
+                phout[(size_t)own] = po + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+                if (more) po = phin[(size_t)own + plane];
             }
             if (kLatePrefetch && more) fetch_pops(z + 1);
         }
@@ -810,32 +836,26 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             float h[27];
             collide(m, P.omega, h);
             const __amdgpu_buffer_rsrc_t dst = plane_rsrc(fout + (size_t)z * pstride, pbytes);
+            uint32_t soff = 0;
 #pragma unroll
-            for (int i = 0; i < 27; i++) bstore<T>(dst, own_xy * ES, i * plane * ES, Pop<S>::enc(h[i]));
+            for (int i = 0; i < 27; i++) {
+                bstore<T>(dst, own_xy * ES, soff, Pop<S>::enc(h[i]));
+                soff += plane * ES;
+                asm volatile("" : "+s"(soff));
+            }
 
             if constexpr (TP) {  // velocity of this step, advects phi in the next one
-                stb<float>(B.uout, own * 4u, m.u[0]);
-                stb<float>(B.uout + N, own * 4u, m.u[1]);
-                stb<float>(B.uout + 2 * (size_t)N, own * 4u, m.u[2]);
+                uout[own] = m.u[0];
+                uout[(size_t)N + own] = m.u[1];
+                uout[2 * (size_t)N + own] = m.u[2];
             }
         }
     }
 }
 
-// One box per launch.  Workgroups are handed to the 8 XCDs round-robin by
-// launch index; XCD j gets a contiguous run of tiles so that neighbouring
-// tiles share that XCD's L2 (halo rows, +-1 shifted rows).
-template <int S, bool TP, bool FRC, bool ML>
-__global__ void __launch_bounds__(NTHREADS) k_step(Params P, Buffers B)
-{
-    const uint32_t H = blockIdx.x, q8 = (uint32_t)P.nblocks / 8u, r8 = (uint32_t)P.nblocks % 8u;
-    const uint32_t xcd = H % 8u, idx = H / 8u;
-    const uint32_t L = (xcd < r8 ? xcd * (q8 + 1u) : r8 * (q8 + 1u) + (xcd - r8) * q8) + idx;
-    step_tile<S, TP, FRC, ML>(P, B, L);
-}
-
-// A batch of independent boxes in one launch: a persistent grid takes work
-// items (box, tile) from a queue; item k belongs to the box b with
+// The step of one or many independent boxes in one launch (a single box is a
+// batch of one): a persistent grid takes work items (box, tile) from a queue,
+// so the load stays balanced to the last item; item k belongs to the box b with
 // first[b] <= k < first[b + 1].  The queue counter of this launch is
 // counter[parity]; the launch clears the other one for the next launch on the
 // stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
@@ -861,7 +881,7 @@ k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, co
             else hi = mid - 1;
         }
         const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<S, TP, FRC, ML, TW>(tab[b], buf[b], item - first[b]);
+        step_tile<S, TP, FRC, ML, TW, true>(tab[b], buf[b], item - first[b]);
     }
 }
 
@@ -1103,16 +1123,6 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
         else if (storage == 1) LBM_DISPATCH_S(1, tp, frc, ml, CALL);           \
         else LBM_DISPATCH_S(2, tp, frc, ml, CALL);                             \
     } while (0)
-
-hipError_t launch_step(const Params &p, int storage, const Buffers &b, hipStream_t s)
-{
-    dim3 grid(p.nblocks), block(TX, TY, 1);
-    const bool tp = p.two_phase != 0, frc = p.n_modes > 0, ml = p.curv_mode == 1;
-#define CALL(S_, TP_, F_, M_) hipLaunchKernelGGL((k_step<S_, TP_, F_, M_>), grid, block, 0, s, p, b);
-    LBM_DISPATCH(storage, tp, frc, ml, CALL);
-#undef CALL
-    return hipGetLastError();
-}
 
 int batch_grid(int storage, bool tp, bool frc, bool ml, int tile)
 {

@@ -54,8 +54,9 @@ struct WLds : MlpW {
     _Float16 w2t[NH][NH];
 };
 
-template <bool TRANSPOSE>
-__device__ void load_weights_t(const uint16_t *__restrict__ w, MlpW &L, _Float16 (*w2t)[NH], int tid, int nthr)
+// WPtr: pointer to the fp16 weight bits (generic, or global address space)
+template <bool TRANSPOSE, class WPtr>
+__device__ void load_weights_t(WPtr w, MlpW &L, _Float16 (*w2t)[NH], int tid, int nthr)
 {
     for (int e = tid; e < NH * KIN; e += nthr) {
         const int n = e / KIN, k = e % KIN;
@@ -78,12 +79,12 @@ __device__ void load_weights_t(const uint16_t *__restrict__ w, MlpW &L, _Float16
     for (int e = tid; e < 16; e += nthr) L.b3[e] = e < NOUT ? (float)h16(w[OB3 + e]) : 0.0f;
 }
 
-__device__ inline void load_weights(const uint16_t *__restrict__ w, WLds &L, int tid, int nthr)
+template <class WPtr> __device__ inline void load_weights(WPtr w, WLds &L, int tid, int nthr)
 {
     load_weights_t<true>(w, L, L.w2t, tid, nthr);
 }
 
-__device__ inline void load_weights(const uint16_t *__restrict__ w, MlpW &L, int tid, int nthr)
+template <class WPtr> __device__ inline void load_weights(WPtr w, MlpW &L, int tid, int nthr)
 {
     load_weights_t<false>(w, L, nullptr, tid, nthr);
 }
