@@ -16,6 +16,9 @@ the launch stream; the median block is reported.  The learned-curvature
 variants run the same workload with the network blend switched on (seeded
 weights: the cost does not depend on their values).
 
+Each variant also reports its error against the FP64 oracle on a 64^3 box of
+the same recipe after 50 steps (relative L2 of u, max |phi| difference).
+
 Prints one JSON line.  MLUPS = N * K / (t * 1e6).
 """
 import argparse
@@ -228,6 +231,29 @@ def copy_gbs(mib=1024, reps=10):
     return 2 * (mib << 20) / dt / 1e9
 
 
+def error_vs_oracle(storage, curv, steps=50, n=64):
+    """Relative L2 error of u (and max |phi| difference) against the FP64
+    oracle after `steps` steps on an n^3 box of the bench recipe."""
+    import oracle as O
+    from paper_2505_01126_amd import lbm
+    import torch
+
+    shape, phi0, u0, params, nb = workload(n, seed=0)
+    g = lbm.Lattice(shape, 0.515, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, **params)
+    w = None
+    if curv == "mlp":
+        w = mlp_weights()
+        g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
+    g.step(steps)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    g.close()
+    o = O.Oracle(shape, 0.515, phi0=phi0, u0=u0, curv_mode=1 if curv == "mlp" else 0, mlp=w, **params)
+    o.step(steps)
+    mo = o.moments()
+    return {"u_rel_l2": float(np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])),
+            "phi_max_abs": float(np.abs(m["phi"] - mo["phi"]).max()), "box": n, "steps": steps}
+
+
 def cpu_baseline(seconds=15.0):
     """The FP64 oracle on a 64^3 box of the same recipe (one d = 16 bubble,
     same parameters and forcing), timed over whole steps until `seconds` pass."""
@@ -329,6 +355,10 @@ def main():
         }
         print(f"# {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%})",
               file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:  # the oracle runs on the host: skipped with it
+            variants[key]["error_vs_oracle"] = error_vs_oracle(st, curv)
+            print(f"#   vs FP64 oracle (64^3, 50 steps): u {variants[key]['error_vs_oracle']['u_rel_l2']:.2e}",
+                  file=sys.stderr, flush=True)
     primary = next(iter(variants))
     v = variants[primary]
     traffic = traffic_for(name, v["storage"]) if v["curvature"] == "fd" else None
