@@ -1,0 +1,109 @@
+"""GPU against the FP64 oracle at the step counts of the benchmark configurations.
+
+* static droplet, 64^3, R = 12, density ratio 10, sigma 0.01, tau 1: 5000 steps
+  (FP32 storage; the velocity of a static droplet is its spurious current,
+  ~1e-5, below the fp16 quantum of the stored populations, so the FP16 bar
+  is not applied to it), plus Laplace's law on the GPU result;
+* forced single-phase turbulence (random solenoidal u0 of rms 0.02, forcing
+  on 0 < |k|^2 <= 4, tau 0.55): 500 steps on 64^3 (the oracle's share of the
+  256^3 configuration), FP32, FP16 and BF16 storage;
+* bubbly turbulence (the bench recipe on 64^3: one bubble of d 16, ratio 10,
+  sigma 0.005, tau 0.515, forcing): 500 steps, FP32 and FP16 storage.
+
+Bars on the relative L2 error of u: 1e-5 (FP32), 1e-3 (FP16), 1e-2 (BF16,
+8-bit mantissa); phi within 1e-5 (FP32) or 1e-3 (16-bit storage: 500 steps of
+advection by a velocity that differs by ~1e-4 relative); sum phi equal to the
+oracle's within 1e-12 relative.  The static droplet's velocity is its
+spurious current (~1e-5, from rounding-level force imbalances), on which a
+relative bar measures rounding rather than the method; its bar is on the
+velocity error against the capillary velocity sigma / (rho_l nu) instead.
+Each oracle run is shared by the storage modes of its case.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_01126_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"f32": 1e-5, "f16": 1e-3, "bf16": 1e-2}
+
+
+def _gpu(shape, tau, steps, storage, **kw):
+    from paper_2505_01126_amd import lbm
+
+    print(f"case shape={shape} tau={tau} steps={steps} storage={storage}", flush=True)
+    g = lbm.Lattice(shape, tau, storage=storage, **kw)
+    g.step(steps)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    r = g.reduce()
+    g.close()
+    return m, r
+
+
+_oracle_cache = {}
+
+
+def _oracle(name, shape, tau, steps, **kw):
+    if name not in _oracle_cache:
+        o = O.Oracle(shape, tau, **kw)
+        o.step(steps)
+        _oracle_cache[name] = (o.moments(), o.reduce())
+    return _oracle_cache[name]
+
+
+def _check(name, m, r, mo, ro, storage, two_phase, u_scale=None):
+    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    msg = f"{name} {storage}: u rel err {e:.3e}"
+    if u_scale is not None:
+        eu = np.abs(m["u"] - mo["u"]).max() / u_scale
+        msg += f", max |u - u_oracle| / u_sigma {eu:.3e} (|u_oracle| max {np.abs(mo['u']).max():.2e})"
+    ok = (eu if u_scale is not None else e) < BARS[storage]
+    if two_phase:
+        dphi = np.abs(m["phi"] - mo["phi"]).max()
+        drift = abs(r[0] - ro[0]) / ro[0]
+        msg += f", phi max abs {dphi:.3e}, sum phi vs oracle {drift:.1e}"
+        ok = ok and dphi < (1e-5 if storage == "f32" else 1e-3) and drift < 1e-12
+    print(msg, flush=True)
+    assert ok, msg
+
+
+def test_static_droplet_5000_steps():
+    shape = (64, 64, 64)
+    phi0, c = I.droplet(shape, 12.0, 4.0, seed=1)
+    kw = dict(phi0=phi0, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    m, r = _gpu(shape, 1.0, 5000, "f32", **kw)
+    mo, ro = _oracle("droplet", shape, 1.0, 5000, **kw)
+    # Laplace's law on the GPU fields: p inside minus p outside vs 2 sigma / R_eff
+    phi, p = m["phi"], m["p"]
+    reff = (3.0 * phi.sum() / (4.0 * math.pi)) ** (1.0 / 3.0)
+    dp = p[phi > 0.99].mean() - p[phi < 0.01].mean()
+    ratio = dp / (2 * 0.01 / reff)
+    print(f"Laplace: dp {dp:.6f}, 2 sigma / R_eff {2 * 0.01 / reff:.6f} (R_eff {reff:.3f}), ratio {ratio:.4f}")
+    nu = (1.0 - 0.5) / 3.0
+    _check("droplet 64^3, 5000 steps", m, r, mo, ro, "f32", True, u_scale=0.01 / (1.0 * nu))
+    assert abs(ratio - 1.0) < 0.05
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_forced_turbulence_500_steps(storage):
+    shape = (64, 64, 64)
+    u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=1)
+    kw = dict(u0=u0, modes=I.forcing_modes(1e-5, seed=2), p0=1.0)
+    m, r = _gpu(shape, 0.55, 500, storage, **kw)
+    mo, ro = _oracle("hit", shape, 0.55, 500, **kw)
+    _check("forced turbulence 64^3, 500 steps", m, r, mo, ro, storage, False)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_bubbly_turbulence_500_steps(storage):
+    import bench
+
+    shape, phi0, u0, params, nb = bench.workload(64)
+    kw = dict(phi0=phi0, u0=u0, **params)
+    m, r = _gpu(shape, 0.515, 500, storage, **kw)
+    mo, ro = _oracle("bubbly", shape, 0.515, 500, **kw)
+    _check("bubbly turbulence 64^3, 500 steps", m, r, mo, ro, storage, True)
