@@ -7,7 +7,9 @@ of Sec. 5.2 at the per-GPU size of the paper's weak-scaling runs (Sec. 4):
 the paper's benchmark viscosity), large-scale forcing on the shells
 0 < |k|^2 <= 4 with seeded phases, initial velocity a seeded solenoidal field of
 rms 0.02.  Populations stored in FP32 (the reported value) and in FP16 / BF16
-(reported beside it); arithmetic is FP32 in every variant.
+(reported beside it); arithmetic is FP32 in every variant.  The phase field
+is stored in FP64, or in int32 fixed point in the ":fix32" variants (4 bytes
+less read and written per site).
 
 A step is one fused kernel launch over the whole box.  Inputs are resident in
 HBM before timing starts; W untimed warm-up steps, then R blocks of K timed
@@ -38,6 +40,21 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per lattice update: 27 population reads + 27 writes,
 # phi FP64 read + write, u FP32 x3 read + write (the advecting velocity)
 BYTES_PER_LUP = {"f32": 27 * 4 * 2 + 8 + 8 + 12 + 12, "f16": 27 * 2 * 2 + 40, "bf16": 27 * 2 * 2 + 40}
+PHI_BYTES_SAVED = {"f64": 0, "fix32": 4 + 4}  # int32 phi: 4 B read + 4 B written instead of 8 + 8
+
+
+def parse_variant(key):
+    """'storage[:curvature][:phi storage]' -> (storage, curvature, phi storage)."""
+    parts = key.split(":")
+    st, curv, phs = parts[0], "fd", "f64"
+    for p in parts[1:]:
+        if p in ("fd", "mlp"):
+            curv = p
+        elif p in PHI_BYTES_SAVED:
+            phs = p
+        else:
+            raise SystemExit(f"bench.py: unknown variant field {p!r} in {key!r}")
+    return st, curv, phs
 KERNEL_SOURCES = ["paper_2505_01126_amd/csrc/lbm_kernels.hip", "paper_2505_01126_amd/csrc/lbm_internal.h"]
 
 
@@ -85,12 +102,13 @@ def mlp_weights(seed=5):
     return w.astype(np.float16).astype(np.float64)
 
 
-def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, zchunk, curv="fd"):
+def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, zchunk, curv="fd", phs="f64"):
     import torch
 
     from paper_2505_01126_amd import lbm
 
-    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, curv_mode=curv, **params)
+    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, curv_mode=curv, phi_storage=phs,
+                    **params)
     if curv == "mlp":
         g.set_mlp(torch.tensor(mlp_weights().astype(np.float16).view(np.int16), device="cuda"))
     r0 = g.reduce()
@@ -231,7 +249,7 @@ def copy_gbs(mib=1024, reps=10):
     return 2 * (mib << 20) / dt / 1e9
 
 
-def error_vs_oracle(storage, curv, steps=50, n=64):
+def error_vs_oracle(storage, curv, phs="f64", steps=50, n=64):
     """Relative L2 error of u (and max |phi| difference) against the FP64
     oracle after `steps` steps on an n^3 box of the bench recipe."""
     import oracle as O
@@ -239,7 +257,7 @@ def error_vs_oracle(storage, curv, steps=50, n=64):
     import torch
 
     shape, phi0, u0, params, nb = workload(n, seed=0)
-    g = lbm.Lattice(shape, 0.515, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, **params)
+    g = lbm.Lattice(shape, 0.515, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, phi_storage=phs, **params)
     w = None
     if curv == "mlp":
         w = mlp_weights()
@@ -288,8 +306,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--repeats", type=int, default=5)
-    ap.add_argument("--storage", default="f32,f16,bf16,f32:mlp,f16:mlp",
-                    help="comma list of storage[:curvature] variants; the first is the reported value")
+    ap.add_argument("--storage", default="f32,f16,bf16,f32:mlp,f16:mlp,f32:fix32,f16:fix32",
+                    help="comma list of storage[:curvature][:phi storage] variants (curvature fd|mlp, phi "
+                         "f64|fix32); the first is the reported value")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -342,26 +361,26 @@ def main():
     name = f"bubbly_hit_{args.size}"
     variants = {}
     for key in [s.strip() for s in args.storage.split(",") if s.strip()]:
-        st, _, curv = key.partition(":")
-        curv = curv or "fd"
+        st, curv, phs = parse_variant(key)
         ms, r0, r1 = time_variant(shape, phi0, u0, params, st, args.steps, args.warmup, args.repeats, tau,
-                                  args.zchunk, curv)
+                                  args.zchunk, curv, phs)
         mlups = N / (ms * 1e-3) / 1e6
-        achieved = BYTES_PER_LUP[st] * N / (ms * 1e-3) / 1e9
+        blup = BYTES_PER_LUP[st] - PHI_BYTES_SAVED[phs]
+        achieved = blup * N / (ms * 1e-3) / 1e9
         variants[key] = {
-            "storage": st, "curvature": curv, "mlups": mlups, "ms_per_step": ms, "bytes_per_lup": BYTES_PER_LUP[st],
-            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS,
+            "storage": st, "curvature": curv, "phi_storage": phs, "mlups": mlups, "ms_per_step": ms,
+            "bytes_per_lup": blup, "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS,
             "phase_volume_drift": abs(r1[0] - r0[0]) / r0[0], "nonfinite": int(r1[9]), "max_u": r1[7],
         }
         print(f"# {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%})",
               file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:  # the oracle runs on the host: skipped with it
-            variants[key]["error_vs_oracle"] = error_vs_oracle(st, curv)
+            variants[key]["error_vs_oracle"] = error_vs_oracle(st, curv, phs)
             print(f"#   vs FP64 oracle (64^3, 50 steps): u {variants[key]['error_vs_oracle']['u_rel_l2']:.2e}",
                   file=sys.stderr, flush=True)
     primary = next(iter(variants))
     v = variants[primary]
-    traffic = traffic_for(name, v["storage"]) if v["curvature"] == "fd" else None
+    traffic = traffic_for(name, v["storage"]) if (v["curvature"], v["phi_storage"]) == ("fd", "f64") else None
     line = {
         "metric": "MLUPS & % HBM roofline, 512^3 bubbly HIT, FP32 vs FP16-stored populations",
         "value": v["mlups"],
@@ -377,7 +396,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "grid": list(shape), "bubbles": nb, "bubble_diameter": 16,
                    "density_ratio": 10, "sigma": 0.005, "tau": tau, "storage": v["storage"],
-                   "curvature": v["curvature"], "parallelism": "single GPU"},
+                   "curvature": v["curvature"], "phi_storage": v["phi_storage"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": v["frac"], "traffic": traffic},
         "variants": variants,

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 #define LBM_NRED 10          /* number of lbm_reduce outputs */
 #define LBM_MAX_MODES 64     /* forcing table rows */
 #define LBM_MLP_NPARAM 6212  /* 27*64+64 + 64*64+64 + 64*4+4 */
@@ -52,6 +52,16 @@ enum {
 /* population storage: FP32, or FP16 / BF16 holding h_i = f_i / w_i - P0
  * (arithmetic is FP32 in every mode; FP32 storage holds the same shifted h_i) */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
+
+/* phase-field storage (two-phase runs; the arithmetic is FP32 in both):
+ *   F64:   FP64 phi; each face and link flux of Eq. (3) is added in FP64, so
+ *          sum phi is conserved to FP64 round-off;
+ *   FIX32: int32 fixed point q = phi * 2^30 (phi in [-2, 2), quantum 2^-30);
+ *          each flux is rounded to nearest on that grid and the two sites of a
+ *          face or link add and subtract the same integer, so sum phi is
+ *          conserved bit for bit; 4 bytes less read and written per site and
+ *          step.  Initial values outside [-2, 2) are clamped. */
+enum { LBM_PHI_F64 = 0, LBM_PHI_FIX32 = 1 };
 
 /* curvature used by the surface-tension force */
 enum { LBM_CURV_FD = 0, LBM_CURV_MLP = 1 };
@@ -77,6 +87,8 @@ typedef struct {
                             read during lbm_init only */
     double mlp_k_lo;     /* MLP blend ramp on |K_FD| (defaults 0.4 .. 0.6 when both are 0) */
     double mlp_k_hi;
+    int32_t phi_storage; /* LBM_PHI_* (ignored in single phase) */
+    int32_t reserved;    /* 0 */
 } lbm_config;
 
 /* LBM_ABI_VERSION of the loaded library. */
@@ -107,7 +119,8 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
 
 /* Fields at the current time n, written to caller device buffers; any pointer
  * may be NULL.  rho and p = p* rho c_s^2 are FP32 [N], u FP32 [3N] SoA with
- * u = j + a/2 (Sec. 2.2), phi FP64 [N]. */
+ * u = j + a/2 (Sec. 2.2), phi FP64 [N] (converted exactly from the fixed-point
+ * storage). */
 int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_phi);
 
 /* Global FP64 statistics at time n (deterministic order of summation):
@@ -182,7 +195,7 @@ int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int n
  * bit-identical fields to the same box advanced alone with lbm_step.
  *
  * Members are lbm_handle's created with lbm_init; they must share storage,
- * two_phase, curv_mode and the presence of a body force, and be on the same
+ * phi_storage, two_phase, curv_mode and the presence of a body force, and be on the same
  * stream (the first member's).  They must outlive the batch.  A member may
  * still be stepped, read or reduced on its own; the batch picks up its state
  * at the next lbm_batch_step. */
@@ -195,8 +208,8 @@ size_t lbm_batch_bytes(int n);
 /* Create a batch of n members (1 <= n <= LBM_BATCH_MAX).  d_table: caller's
  * device buffer of table_bytes >= lbm_batch_bytes(n), 256-byte aligned, owned
  * by the caller and used by the batch until lbm_batch_destroy.  Errors:
- * LBM_EINVAL (n, NULL or repeated member, mixed storage / two_phase /
- * curv_mode / forcing / stream), LBM_ENOSPACE, LBM_EHIP. */
+ * LBM_EINVAL (n, NULL or repeated member, mixed storage / phi storage /
+ * two_phase / curv_mode / forcing / stream), LBM_ENOSPACE, LBM_EHIP. */
 int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d_table, size_t table_bytes);
 
 /* Advance every member by nsteps (>= 0), asynchronously on the members' stream.

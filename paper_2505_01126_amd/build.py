@@ -2,6 +2,7 @@
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,13 +20,26 @@ HIPCC_FLAGS = [
 
 def build(verbose=False, extra=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(PKG, "csrc", s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + list(extra or []) + [
-        "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"), "-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    # one object per source, compiled concurrently, then one link
+    with tempfile.TemporaryDirectory() as d:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(d, src.replace(".hip", ".o"))
+            cmd = [hipcc] + [f for f in HIPCC_FLAGS if f != "-shared"] + list(extra or []) + inc + [
+                "-c", "-o", obj, os.path.join(PKG, "csrc", src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [cmd for cmd, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     probe = [hipcc] + [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")] + [
         "-o", PROBE + ".tmp", os.path.join(PKG, "csrc", "bw_probe.hip")]

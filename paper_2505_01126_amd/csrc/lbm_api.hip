@@ -43,8 +43,9 @@ Layout layout_of(const lbm_config &c)
     L.f[0] = take(27 * N * elem_bytes(c.storage));
     L.f[1] = take(27 * N * elem_bytes(c.storage));
     if (c.two_phase) {
-        L.phi[0] = take(8 * N);
-        L.phi[1] = take(8 * N);
+        const size_t pb = c.phi_storage == LBM_PHI_FIX32 ? 4 : 8;
+        L.phi[0] = take(pb * N);
+        L.phi[1] = take(pb * N);
         L.u[0] = take(12 * N);
         L.u[1] = take(12 * N);
     } else {
@@ -77,6 +78,7 @@ const char *validate(const lbm_config *c)
     if (c->two_phase != 0 && c->two_phase != 1) return "two_phase must be 0 or 1";
     if (c->curv_mode != LBM_CURV_FD && c->curv_mode != LBM_CURV_MLP) return "curv_mode must be FD or MLP";
     if (c->curv_mode == LBM_CURV_MLP && !c->two_phase) return "MLP curvature needs two_phase";
+    if (c->phi_storage != LBM_PHI_F64 && c->phi_storage != LBM_PHI_FIX32) return "phi_storage must be F64 or FIX32";
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return "tau must be > 1/2";
     if (!(c->rho_l > 0.0) || !std::isfinite(c->rho_l)) return "rho_l must be > 0";
     if (c->two_phase) {
@@ -119,7 +121,7 @@ struct lbm_batch {
     char *table = nullptr;
     size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
     int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
-    bool tp = false, frc = false, ml = false, dirty = true;
+    bool tp = false, frc = false, ml = false, fix = false, dirty = true;
     hipGraphExec_t exec = nullptr;
     std::string err;
 
@@ -159,7 +161,7 @@ struct lbm_handle {
     std::string err;
 
     void *f(int k) { return ws + L.f[k]; }
-    double *phi(int k) { return cfg.two_phase ? (double *)(ws + L.phi[k]) : nullptr; }
+    void *phi(int k) { return cfg.two_phase ? (void *)(ws + L.phi[k]) : nullptr; }
     float *u(int k) { return cfg.two_phase ? (float *)(ws + L.u[k]) : nullptr; }
 
     int fail(int code, const std::string &msg)
@@ -226,6 +228,7 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
     P.two_phase = cfg->two_phase;
     P.curv_mode = cfg->curv_mode;
     P.n_modes = cfg->n_modes;
+    P.phi_fix = cfg->two_phase && cfg->phi_storage == LBM_PHI_FIX32;
     P.omega = (float)(1.0 / cfg->tau);
     P.p0 = (float)cfg->p0;
     P.rho_l = (float)cfg->rho_l;
@@ -444,10 +447,10 @@ int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int n
     long long *counts = (long long *)(h->ws + h->L.hcount);
     long long *offsets = counts + lbm::HARVEST_BLOCKS;
     std::vector<long long> hc(blocks), ho(blocks);
-    const double *phi = h->phi(h->cur);
+    const void *phi = h->phi(h->cur);
     hipError_t e = hipMemcpyAsync(h->ws + h->L.sph, sph.data(), sizeof(double) * 4 * nb, hipMemcpyHostToDevice,
                                   h->stream);
-    if (e == hipSuccess) e = lbm::launch_harvest_count(phi, N, chunk, blocks, counts, h->stream);
+    if (e == hipSuccess) e = lbm::launch_harvest_count(phi, h->P.phi_fix, N, chunk, blocks, counts, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hc.data(), counts, sizeof(long long) * blocks, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -574,7 +577,7 @@ hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
 {
     const int n = (int)b->m.size();
     return lbm::launch_step_batch(b->d_tab(), b->d_buf() + (size_t)parity * n, b->d_first(), n, b->d_counter(),
-                                  parity, b->storage, b->tp, b->frc, b->ml, b->tile, b->grid, s);
+                                  parity, b->storage, b->tp, b->frc, b->ml, b->fix, b->tile, b->grid, s);
 }
 
 void batch_advance(lbm_batch *b, int64_t k)
@@ -622,8 +625,9 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
     for (lbm_handle *h : m) {
         if (!h) return bad(LBM_EINVAL, "NULL member");
         if (h->cfg.storage != h0->cfg.storage || h->cfg.two_phase != h0->cfg.two_phase ||
-            h->cfg.curv_mode != h0->cfg.curv_mode || (h->cfg.n_modes > 0) != (h0->cfg.n_modes > 0))
-            return bad(LBM_EINVAL, "members differ in storage, two_phase, curv_mode or forcing");
+            h->cfg.curv_mode != h0->cfg.curv_mode || (h->cfg.n_modes > 0) != (h0->cfg.n_modes > 0) ||
+            h->P.phi_fix != h0->P.phi_fix)
+            return bad(LBM_EINVAL, "members differ in storage, phi storage, two_phase, curv_mode or forcing");
         if (h->stream != h0->stream) return bad(LBM_EINVAL, "members are on different streams");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch();
@@ -640,8 +644,9 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
     b->tp = h0->cfg.two_phase != 0;
     b->frc = h0->cfg.n_modes > 0;
     b->ml = h0->cfg.curv_mode == LBM_CURV_MLP;
+    b->fix = h0->P.phi_fix != 0;
     for (lbm_handle *h : m) b->P.push_back(h->P);
-    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->tile);
+    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, b->tile);
     if (b->grid <= 0) {
         delete b;
         return bad(LBM_EHIP, "occupancy query failed");
@@ -716,7 +721,7 @@ int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *tile_out, int *zc
     for (lbm_handle *h : b->m)
         shapes.push_back(std::to_string(h->cfg.nx) + "x" + std::to_string(h->cfg.ny) + "x" + std::to_string(h->cfg.nz));
     std::sort(shapes.begin(), shapes.end());
-    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d");
+    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d") + (b->fix ? "q" : "");
     for (const std::string &sh : shapes) key += "," + sh;
     auto apply = [&](int tile, int zc) -> int { return lbm_batch_set_tiling(b, tile, zc); };
     int best_tile = -1, best_zc = -1;
@@ -772,7 +777,7 @@ int lbm_batch_set_tiling(lbm_batch *b, int tile, int zchunk)
     if (!b) return LBM_EINVAL;
     if (tile != 64 && tile != 32) return b->fail(LBM_EINVAL, "tile must be 64 or 32");
     if (zchunk < 1) return b->fail(LBM_EINVAL, "zchunk must be >= 1");
-    const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, tile);
+    const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, tile);
     if (grid <= 0) return b->fail(LBM_EHIP, "occupancy query failed");
     for (lbm::Params &P : b->P) set_tiling(P, tile, zchunk);
     b->tile = tile;

@@ -25,10 +25,22 @@ constexpr int RED_BLOCKS = 1024;  // fixed grid of the reduction (deterministic 
 // A workgroup row is one wave, so the row coefficients are wave-uniform.
 constexpr int FROW = 16;
 
+// Fixed-point phase field: phi = q * 2^-30 with q an int32, so phi in [-2, 2)
+// with a quantum of 9.3e-10.  Sums of q are exact, so the phase volume of a
+// run with this storage is conserved bit for bit.
+constexpr int PHI_FIX_BITS = 30;
+
+// phi of site s as FP64 (exact in both storages)
+__device__ __forceinline__ double phi_load(const void *phi, uint32_t s, int fix)
+{
+    return fix ? (double)((const int32_t *)phi)[s] * 0x1p-30 : ((const double *)phi)[s];
+}
+
 // Scalar parameters of one configuration, passed by value to every kernel.
 struct Params {
     int nx, ny, nz, zchunk;
-    int two_phase, curv_mode, n_modes, pad;
+    int two_phase, curv_mode, n_modes;
+    int phi_fix;    // 1: phi held as int32 fixed point q = phi * 2^PHI_FIX_BITS, 0: FP64
     int gx, gy, gz, nblocks;  // step-kernel tile grid (x tiles, y tiles, z chunks)
     float omega;    // 1 / tau
     float p0;       // pressure gauge / storage shift
@@ -46,21 +58,22 @@ struct Params {
 struct Buffers {
     const void *fin;
     void *fout;
-    const double *phin;
-    double *phout;
+    const void *phin;  // FP64 or int32 fixed point (Params::phi_fix)
+    void *phout;
     const float *uin;
     float *uout;
 };
 
-hipError_t launch_init(const Params &p, int storage, void *fout, double *phi_out, float *u_out, const double *phi0,
+hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,
                        const double *u0, const double *ps0, hipStream_t s);
 // the time step of one or many boxes in one persistent launch (see k_step_batch)
 // tile: workgroup tile width in x, 64 (64 x 4 sites) or 32 (32 x 8)
-int batch_grid(int storage, bool tp, bool frc, bool ml, int tile);
+// fix: phi held as int32 fixed point (two-phase only)
+int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, int tile);
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
-                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int tile,
-                             int grid, hipStream_t s);
-hipError_t launch_moments(const Params &p, int storage, const void *fin, const double *phi, float *rho, float *pr,
+                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, bool fix,
+                             int tile, int grid, hipStream_t s);
+hipError_t launch_moments(const Params &p, int storage, const void *fin, const void *phi, float *rho, float *pr,
                           float *u, double *phi_out, hipStream_t s);
 constexpr int HARVEST_BLOCKS = 1024;
 constexpr int MAX_SPHERES = 1024;
@@ -70,12 +83,12 @@ hipError_t launch_mlp_backward(const uint16_t *w, const uint16_t *x, const float
                                float *loss, float *partial, hipStream_t s);
 hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, uint16_t *w16, float lr, float b1, float b2,
                            float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_harvest_count(const double *phi, uint32_t N, uint32_t chunk, int blocks, long long *counts,
+hipError_t launch_harvest_count(const void *phi, int fix, uint32_t N, uint32_t chunk, int blocks, long long *counts,
                                 hipStream_t s);
-hipError_t launch_harvest_write(const Params &p, const double *phi, uint32_t chunk, int blocks,
+hipError_t launch_harvest_write(const Params &p, const void *phi, uint32_t chunk, int blocks,
                                 const long long *offsets, const void *sph, int nb, uint16_t *X, float *Y, int64_t cap,
                                 hipStream_t s);
-hipError_t launch_reduce(const Params &p, int storage, const void *fin, const double *phi, double *partials,
+hipError_t launch_reduce(const Params &p, int storage, const void *fin, const void *phi, double *partials,
                          double *out, hipStream_t s);
 
 }  // namespace lbm

@@ -15,7 +15,9 @@
 // evaluated by contraction-free code from identical operands on both sides of
 // the link (or once, shared through LDS), so the two sites see bit-identical
 // values; the fluxes are accumulated in FP64 into the FP64 phi, so sum phi is
-// conserved to FP64 round-off.
+// conserved to FP64 round-off, or, with the int32 fixed-point phi, rounded
+// once each to the fixed-point grid and summed exactly, so sum phi is
+// conserved bit for bit.
 //
 // Instruction economy: the D3Q27 weights are a tensor product,
 // w(c) = w1(cx) w1(cy) w1(cz) with w1(0) = 2/3, w1(+-1) = 1/6, so the moments
@@ -23,6 +25,8 @@
 // axis by axis, and the post-collision populations, a quadratic polynomial in
 // c, are generated the same way.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lbm_internal.h"
 #include "lbm_mlp_device.h"
@@ -99,6 +103,26 @@ template <class T> __device__ __forceinline__ const LBM_GLOBAL T *gconst(const T
     return (const LBM_GLOBAL T *)p;
 }
 template <class T> __device__ __forceinline__ LBM_GLOBAL T *gmut(T *p) { return (LBM_GLOBAL T *)p; }
+
+// Phase-field storage of the step: FP64 (fluxes summed in FP64), or int32
+// fixed point q = phi 2^30 (each flux rounded to nearest on that grid, summed
+// in wrapping 32-bit integers, so the two sites of a link add and subtract
+// exactly the same integer).
+template <bool FX> struct PhiStore;
+template <> struct PhiStore<false> {
+    using T = double;    // stored value
+    using Acc = double;  // flux accumulator
+    __device__ static float f32(T v) { return (float)v; }
+    __device__ static Acc flux(float f) { return (double)f; }
+    __device__ static T add(T phi, Acc d) { return phi + d; }
+};
+template <> struct PhiStore<true> {
+    using T = int32_t;
+    using Acc = uint32_t;
+    __device__ static float f32(T q) { return (float)q * 0x1p-30f; }
+    __device__ static Acc flux(float f) { return (uint32_t)(int32_t)__builtin_rintf(f * 0x1p30f); }
+    __device__ static T add(T q, Acc d) { return (int32_t)((uint32_t)q + d); }
+};
 
 // Raw buffer access to one z plane of populations (27 rows of nx * ny): the
 // row offset i * plane goes in the scalar offset, the in-plane offset in the
@@ -519,10 +543,13 @@ __device__ __forceinline__ void lds_barrier()
 // One work item: the xy tile and z chunk with linear index L (x tile fastest,
 // then y tile, then z chunk) of one box.  Every thread of the workgroup calls
 // it; it leaves no LDS state that the next call relies on.
-template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0)>
+template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0), bool FX = false>
 __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L)
 {
     using T = typename Pop<S>::T;
+    using PS = PhiStore<FX>;
+    using PT = typename PS::T;
+    using AT = typename PS::Acc;
     using TL = Tile<TW>;
     constexpr int TXW = TL::X, TYW = TL::Y, PX = TL::PX, PLANE = TL::PLANE, QX = TL::QX, QPLANE = TL::QPLANE,
                   LOADS = TL::LOADS, QPTS = TL::QPTS, NXF = TL::NXF, NYF = TL::NYF, NFACE = TL::NFACE,
@@ -550,8 +577,8 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const LBM_GLOBAL float *__restrict__ ux_in = gconst(B.uin);
     const LBM_GLOBAL float *__restrict__ uy_in = ux_in + N;
     const LBM_GLOBAL float *__restrict__ uz_in = ux_in + 2 * (size_t)N;
-    const LBM_GLOBAL double *__restrict__ phin = gconst(B.phin);
-    LBM_GLOBAL double *__restrict__ phout = gmut(B.phout);
+    const LBM_GLOBAL PT *__restrict__ phin = gconst((const PT *)B.phin);
+    LBM_GLOBAL PT *__restrict__ phout = gmut((PT *)B.phout);
     LBM_GLOBAL float *__restrict__ uout = gmut(B.uout);
 
     // with one x-row per wave the row is wave-uniform (scalar forcing loads)
@@ -607,13 +634,13 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
     bool f_isx[FROUNDS];
-    double phn[LOADS];      // prefetched phi plane
+    PT phn[LOADS];          // prefetched phi plane
     float f_ul[FROUNDS], f_ur[FROUNDS];  // prefetched face velocities
     float jz_left = 0.f, uz_c = 0.f, uz_n = 0.f;
-    double po = 0.0;        // prefetched own phi
+    PT po = 0;              // prefetched own phi
 
     auto fetch_plane = [&](int z) {
-        const LBM_GLOBAL double *src = phin + (size_t)modi(z, nz) * plane;
+        const LBM_GLOBAL PT *src = phin + (size_t)modi(z, nz) * plane;
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
@@ -625,7 +652,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 #pragma unroll
         for (int k = 0; k < LOADS; k++) {
             const int e = tid + k * NTHREADS;
-            if (e < PLANE) dst[e] = (float)phn[k];
+            if (e < PLANE) dst[e] = PS::f32(phn[k]);
         }
     };
     auto fetch_face_u = [&](int z) {
@@ -759,16 +786,16 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
-                // four independent FP64 partial sums keep the dependent add chains short
-                double acc[4];
-                acc[0] = (double)sjx[ty * (TXW + 1) + tx] - (double)sjx[ty * (TXW + 1) + tx + 1];
-                acc[0] += (double)sjy[ty * TXW + tx] - (double)sjy[(ty + 1) * TXW + tx];
+                // four independent partial sums keep the dependent add chains short
+                AT acc[4];
+                acc[0] = PS::flux(sjx[ty * (TXW + 1) + tx]) - PS::flux(sjx[ty * (TXW + 1) + tx + 1]);
+                acc[0] += PS::flux(sjy[ty * TXW + tx]) - PS::flux(sjy[(ty + 1) * TXW + tx]);
                 {
                     float v[6];
 #pragma unroll
                     for (int k = 0; k < 6; k++) v[k] = sphi[ring(z - 2 + k)][lc];
                     const float jr = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], uz_c, uz_n);
-                    acc[1] = (double)jz_left - (double)jr;
+                    acc[1] = PS::flux(jz_left) - PS::flux(jr);
                     jz_left = jr;
                     uz_c = uz_n;
                     if (more) uz_n = uz_in[(uint32_t)wrapi(z + 2, nz) * plane + own_xy];
@@ -798,7 +825,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         const float4 qs = (CZ(I) > 0 ? q0 : q1)[qc - CY(I) * QX - CX(I)];                             \
         const float fo = link_flux<I>(ph[13], ph[I], qo, qn, d6w[C2(I)], k3w[C2(I)]);                 \
         const float fi = link_flux<I>(ph[26 - I], ph[13], qs, qo, d6w[C2(I)], k3w[C2(I)]);            \
-        const double d = (double)fi - (double)fo;                                                     \
+        const AT d = PS::flux(fi) - PS::flux(fo);                                                     \
         if constexpr (I == 14 || I == 15) acc[I & 3] = d;                                             \
         else acc[I & 3] += d;                                                                         \
     }
@@ -806,7 +833,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
                 }
-                phout[(size_t)own] = po + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+                phout[(size_t)own] = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
                 if (more) po = phin[(size_t)own + plane];
             }
             if (kLatePrefetch && more) fetch_pops(z + 1);
@@ -859,7 +886,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 // first[b] <= k < first[b + 1].  The queue counter of this launch is
 // counter[parity]; the launch clears the other one for the next launch on the
 // stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
-template <int S, bool TP, bool FRC, bool ML, int TW>
+template <int S, bool TP, bool FRC, bool ML, int TW, bool FX>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(ML ? 1 : 3)))
 k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
              int nbox, uint32_t *counter, int parity)
@@ -881,7 +908,7 @@ k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, co
             else hi = mid - 1;
         }
         const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<S, TP, FRC, ML, TW, true>(tab[b], buf[b], item - first[b]);
+        step_tile<S, TP, FRC, ML, TW, true, FX>(tab[b], buf[b], item - first[b]);
     }
 }
 
@@ -889,7 +916,7 @@ k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, co
 // f^0 = f^eq(p*0, u0) + w H : A0 / (2 c_s^4), A0 = -c_s^2 tau (grad u0 + grad u0^T),
 // written pre-shifted (slot of x - c_i) so that the first pull yields f^0 at x.
 template <int S>
-__global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double *phi_out, float *u_out,
+__global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, void *phi_out, float *u_out,
                                                    const double *phi0, const double *u0, const double *ps0)
 {
     using T = typename Pop<S>::T;
@@ -932,7 +959,13 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double
         const double h = dp + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2 + 4.5 * hA;
         fout[pop_index(P, i, nb(-CX(i), -CY(i), -CZ(i)))] = Pop<S>::enc((float)h);
     }
-    if (phi_out) phi_out[s] = P.two_phase ? phi0[s] : 0.0;
+    if (phi_out) {
+        const double ph = P.two_phase ? phi0[s] : 0.0;
+        if (P.phi_fix)  // nearest point of the fixed-point grid, clamped to its range [-2, 2)
+            ((int32_t *)phi_out)[s] = (int32_t)__builtin_rint(fmin(fmax(ph * 0x1p30, -0x1p31), 0x1p31 - 1.0));
+        else
+            ((double *)phi_out)[s] = ph;
+    }
     if (u_out)
         for (int a = 0; a < 3; a++) u_out[(size_t)a * N + s] = (float)u[a];
 }
@@ -942,7 +975,7 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, double
 // Every lane of the wave calls this together (the network stage is a
 // wave-wide MFMA); lanes with valid == false only take part in that stage.
 template <int S, bool TP, bool FRC, bool ML>
-__device__ __forceinline__ void site_state(const Params &P, const void *fin_, const double *phi, uint32_t s,
+__device__ __forceinline__ void site_state(const Params &P, const void *fin_, const void *phi, uint32_t s,
                                            bool valid, Macro &m, const MlpW &W, MlpWave &wv, int lane)
 {
     using T = typename Pop<S>::T;
@@ -965,7 +998,7 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
         moments10(hv, M);
         if constexpr (TP) {
 #pragma unroll
-            for (int i = 0; i < 27; i++) ph[i] = (float)phi[nb(CX(i), CY(i), CZ(i))];
+            for (int i = 0; i < 27; i++) ph[i] = (float)phi_load(phi, nb(CX(i), CY(i), CZ(i)), P.phi_fix);
             phi_stencil(ph, G);
             if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
         }
@@ -991,7 +1024,7 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
 }
 
 template <int S, bool TP, bool FRC, bool ML>
-__global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin, const double *phi, float *rho,
+__global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin, const void *phi, float *rho,
                                                       float *pr, float *u, double *phi_out)
 {
     __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
@@ -1014,13 +1047,16 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin,
         u[(size_t)N + s] = m.u[1];
         u[2 * (size_t)N + s] = m.u[2];
     }
-    if (phi_out) phi_out[s] = TP ? phi[s] : 0.0;
+    if (phi_out) phi_out[s] = TP ? phi_load(phi, s, P.phi_fix) : 0.0;
 }
 
 // FP64 partial sums per block over a fixed grid-stride partition, combined in
-// a fixed order: the result does not depend on scheduling.
+// a fixed order: the result does not depend on scheduling.  With the
+// fixed-point phi, sum phi is accumulated as the integer sum of q (exact in
+// the FP64 block partials, which stay below 2^53, and in the final int64 sum),
+// so it is a function of that integer alone.
 template <int S, bool TP, bool FRC, bool ML>
-__global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, const double *phi, double *partials)
+__global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, const void *phi, double *partials)
 {
     __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
     MlpW &W = *(MlpW *)mlp_raw;
@@ -1041,7 +1077,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, 
         site_state<S, TP, FRC, ML>(P, fin, phi, valid ? s : 0u, valid, m, W, wv[threadIdx.x >> 6],
                                    threadIdx.x & 63);
         if (!valid) continue;
-        const double ph = TP ? phi[s] : 0.0;
+        const double ph = TP ? phi_load(phi, s, P.phi_fix) : 0.0;
         const double r = m.rho, pstar = (double)P.p0 + (double)m.dp;
         const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
         const bool bad = !isfinite(pstar) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz) || !isfinite(ph);
@@ -1050,7 +1086,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, 
             continue;
         }
         const double u2 = ux * ux + uy * uy + uz * uz;
-        acc[0] += ph;
+        acc[0] += P.phi_fix ? ph * 0x1p30 : ph;
         acc[1] += r;
         acc[2] += pstar;
         acc[3] += r * ux;
@@ -1077,20 +1113,25 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, 
     if (threadIdx.x < NRED) partials[(size_t)blockIdx.x * NRED + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partials, int nblocks, double *out)
+__global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partials, int nblocks, int fix, double *out)
 {
     __shared__ double red[NRED][NTHREADS];
+    __shared__ long long redq[NTHREADS];
     double acc[NRED];
+    long long q = 0;  // fixed-point phi: integer sum of q
 #pragma unroll
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += NTHREADS)
+    for (int b = threadIdx.x; b < nblocks; b += NTHREADS) {
 #pragma unroll
         for (int k = 0; k < NRED; k++) {
             const double v = partials[(size_t)b * NRED + k];
             acc[k] = (k == 7 || k == 8) ? fmax(acc[k], v) : acc[k] + v;
         }
+        if (fix) q += (long long)partials[(size_t)b * NRED];
+    }
 #pragma unroll
     for (int k = 0; k < NRED; k++) red[k][threadIdx.x] = acc[k];
+    redq[threadIdx.x] = q;
     __syncthreads();
     for (int w = NTHREADS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
@@ -1099,10 +1140,12 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
                 const double o = red[k][threadIdx.x + w];
                 red[k][threadIdx.x] = (k == 7 || k == 8) ? fmax(red[k][threadIdx.x], o) : red[k][threadIdx.x] + o;
             }
+            redq[threadIdx.x] += redq[threadIdx.x + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x < NRED) out[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < NRED)
+        out[threadIdx.x] = (fix && threadIdx.x == 0) ? (double)redq[0] * 0x1p-30 : red[threadIdx.x][0];
 }
 
 // --------------------------------------------------------------- launchers
@@ -1124,45 +1167,51 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
         else LBM_DISPATCH_S(2, tp, frc, ml, CALL);                             \
     } while (0)
 
-int batch_grid(int storage, bool tp, bool frc, bool ml, int tile)
+// the step kernel also takes the phi storage (fixed point exists only with the phase field)
+#define LBM_STEP_CALL(S_, TP_, F_, M_)                                                          \
+    {                                                                                           \
+        if (TP_ && fix) STEP_CALL(S_, TP_, F_, M_, true) else STEP_CALL(S_, TP_, F_, M_, false) \
+    }
+
+int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, int tile)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-#define CALL(S_, TP_, F_, M_)                                                                              \
-    {                                                                                                      \
-        if (tile == 32)                                                                                    \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 32>,  \
-                                                               NTHREADS, 0);                               \
-        else                                                                                               \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 64>,  \
-                                                               NTHREADS, 0);                               \
+#define STEP_CALL(S_, TP_, F_, M_, X_)                                                                         \
+    {                                                                                                          \
+        if (tile == 32)                                                                                        \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 32, X_>,  \
+                                                               NTHREADS, 0);                                   \
+        else                                                                                                   \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<S_, TP_, F_, M_, 64, X_>,  \
+                                                               NTHREADS, 0);                                   \
     }
-    LBM_DISPATCH(storage, tp, frc, ml, CALL);
-#undef CALL
+    LBM_DISPATCH(storage, tp, frc, ml, LBM_STEP_CALL);
+#undef STEP_CALL
     return per_cu * cus;
 }
 
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
-                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, int tile,
-                             int grid, hipStream_t s)
+                             uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, bool fix,
+                             int tile, int grid, hipStream_t s)
 {
     dim3 g(grid), block(tile, NTHREADS / tile, 1);
-#define CALL(S_, TP_, F_, M_)                                                                              \
-    {                                                                                                      \
-        if (tile == 32)                                                                                    \
-            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 32>), g, block, 0, s, tab, buf, first, nbox,  \
-                               counter, parity);                                                           \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 64>), g, block, 0, s, tab, buf, first, nbox,  \
-                               counter, parity);                                                           \
+#define STEP_CALL(S_, TP_, F_, M_, X_)                                                                         \
+    {                                                                                                          \
+        if (tile == 32)                                                                                        \
+            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 32, X_>), g, block, 0, s, tab, buf, first, nbox,  \
+                               counter, parity);                                                               \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_step_batch<S_, TP_, F_, M_, 64, X_>), g, block, 0, s, tab, buf, first, nbox,  \
+                               counter, parity);                                                               \
     }
-    LBM_DISPATCH(storage, tp, frc, ml, CALL);
-#undef CALL
+    LBM_DISPATCH(storage, tp, frc, ml, LBM_STEP_CALL);
+#undef STEP_CALL
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Params &p, int storage, void *fout, double *phi_out, float *u_out, const double *phi0,
+hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,
                        const double *u0, const double *ps0, hipStream_t s)
 {
     const uint32_t N = (uint32_t)p.nx * p.ny * p.nz;
@@ -1173,7 +1222,7 @@ hipError_t launch_init(const Params &p, int storage, void *fout, double *phi_out
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const Params &p, int storage, const void *fin, const double *phi, float *rho, float *pr,
+hipError_t launch_moments(const Params &p, int storage, const void *fin, const void *phi, float *rho, float *pr,
                           float *u, double *phi_out, hipStream_t s)
 {
     const uint32_t N = (uint32_t)p.nx * p.ny * p.nz;
@@ -1186,7 +1235,7 @@ hipError_t launch_moments(const Params &p, int storage, const void *fin, const d
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const Params &p, int storage, const void *fin, const double *phi, double *partials,
+hipError_t launch_reduce(const Params &p, int storage, const void *fin, const void *phi, double *partials,
                          double *out, hipStream_t s)
 {
     dim3 grid(RED_BLOCKS), block(NTHREADS);
@@ -1197,7 +1246,7 @@ hipError_t launch_reduce(const Params &p, int storage, const void *fin, const do
 #undef CALL
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), block, 0, s, partials, (int)RED_BLOCKS, out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), block, 0, s, partials, (int)RED_BLOCKS, p.phi_fix, out);
     return hipGetLastError();
 }
 

@@ -244,13 +244,13 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ w, float *
 // offset + rank within the range (workgroup prefix over waves).
 __device__ __forceinline__ bool is_interface(double p) { return p > 0.02 && p < 0.98; }
 
-__global__ void __launch_bounds__(256) k_harvest_count(const double *__restrict__ phi, uint32_t N, uint32_t chunk,
-                                                       long long *__restrict__ counts)
+__global__ void __launch_bounds__(256) k_harvest_count(const void *__restrict__ phi, int fix, uint32_t N,
+                                                       uint32_t chunk, long long *__restrict__ counts)
 {
     __shared__ int wsum[4];
     const uint32_t b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, N);
     int cnt = 0;
-    for (uint32_t s = b0 + threadIdx.x; s < b1; s += 256) cnt += is_interface(phi[s]) ? 1 : 0;
+    for (uint32_t s = b0 + threadIdx.x; s < b1; s += 256) cnt += is_interface(phi_load(phi, s, fix)) ? 1 : 0;
     // wave sums then fixed-order block sum
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
@@ -262,7 +262,7 @@ struct Sphere {
     double x, y, z, r;
 };
 
-__global__ void __launch_bounds__(256) k_harvest_write(Params P, const double *__restrict__ phi, uint32_t chunk,
+__global__ void __launch_bounds__(256) k_harvest_write(Params P, const void *__restrict__ phi, uint32_t chunk,
                                                        const long long *__restrict__ offsets,
                                                        const Sphere *__restrict__ sph, int nb,
                                                        uint16_t *__restrict__ X, float *__restrict__ Y, int64_t cap)
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) k_harvest_write(Params P, const double *_
     long long base = offsets[blockIdx.x];
     for (uint32_t s0 = b0; s0 < b1; s0 += 256) {
         const uint32_t s = s0 + threadIdx.x;
-        const bool sel = s < b1 && is_interface(phi[s]);
+        const bool sel = s < b1 && is_interface(phi_load(phi, s, P.phi_fix));
         const unsigned long long ballot = __ballot(sel);
         const int rank = __popcll(ballot & ((1ull << lane) - 1ull));
         if (lane == 0) wcnt[wave] = __popcll(ballot);
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(256) k_harvest_write(Params P, const double *_
                 for (int i = 0; i < 27; i++) {
                     const int dx = i % 3 - 1, dy = (i / 3) % 3 - 1, dz = i / 9 - 1;
                     const int xx = (x + dx + nx) % nx, yy = (y + dy + ny) % ny, zz = (z + dz + nz) % nz;
-                    const double p = phi[(size_t)zz * plane + (size_t)yy * nx + xx];
+                    const double p = phi_load(phi, (uint32_t)zz * plane + (uint32_t)yy * nx + xx, P.phi_fix);
                     xr[i] = __builtin_bit_cast(uint16_t, (_Float16)(2.0 * p - 1.0));  // one rounding
                 }
                 for (int i = 27; i < KIN; i++) xr[i] = 0;
@@ -371,14 +371,14 @@ hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, uint16_
     return hipGetLastError();
 }
 
-hipError_t launch_harvest_count(const double *phi, uint32_t N, uint32_t chunk, int blocks, long long *counts,
+hipError_t launch_harvest_count(const void *phi, int fix, uint32_t N, uint32_t chunk, int blocks, long long *counts,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_harvest_count, dim3(blocks), dim3(256), 0, s, phi, N, chunk, counts);
+    hipLaunchKernelGGL(k_harvest_count, dim3(blocks), dim3(256), 0, s, phi, fix, N, chunk, counts);
     return hipGetLastError();
 }
 
-hipError_t launch_harvest_write(const Params &p, const double *phi, uint32_t chunk, int blocks,
+hipError_t launch_harvest_write(const Params &p, const void *phi, uint32_t chunk, int blocks,
                                 const long long *offsets, const void *sph, int nb, uint16_t *X, float *Y, int64_t cap,
                                 hipStream_t s)
 {

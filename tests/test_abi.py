@@ -32,7 +32,27 @@ def test_abi_version_and_constants():
     assert lbm.lbm_abi_version() == ver
     assert int(re.search(r"#define LBM_NRED (\d+)", text).group(1)) == lbm.NRED
     assert int(re.search(r"#define LBM_MLP_NPARAM (\d+)", text).group(1)) == lbm.MLP_NPARAM
-    assert C.sizeof(lbm.lbm_config) == 112
+    assert C.sizeof(lbm.lbm_config) == 120
+
+
+def test_config_struct_matches_header(tmp_path):
+    """The ctypes mirror of lbm_config has the C compiler's size and offsets."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    fields = [f for f, _ in lbm.lbm_config._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(lbm_config));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(lbm_config, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == C.sizeof(lbm.lbm_config)
+    assert out[1:] == [getattr(lbm.lbm_config, f).offset for f in fields]
 
 
 def test_workspace_bytes_counts_state():
@@ -44,11 +64,15 @@ def test_workspace_bytes_counts_state():
     two = lbm.lbm_workspace_bytes(cfg2)
     assert two >= 2 * 27 * 2 * N + 2 * 8 * N + 2 * 12 * N
     assert two < 2 * 27 * 2 * N + 2 * 8 * N + 2 * 12 * N + (1 << 20)
+    # int32 fixed-point phi: two 4-byte fields instead of two 8-byte ones
+    cfg3, _ = lbm.make_config((64, 64, 64), 0.8, two_phase=True, storage="f16", phi_storage="fix32")
+    assert lbm.lbm_workspace_bytes(cfg3) == two - 2 * 4 * N
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)),
                                 dict(tau=0.8, shape=(8, 4097, 4097)),
-                                dict(tau=0.8, storage="f16", modes=[[3, 0, 0] + [0] * 6])])
+                                dict(tau=0.8, storage="f16", modes=[[3, 0, 0] + [0] * 6]),
+                                dict(tau=0.8, two_phase=True, phi_storage=2)])
 def test_invalid_configs_rejected_on_host(kw):
     shape = kw.pop("shape", (16, 16, 16))
     tau = kw.pop("tau")

@@ -51,8 +51,9 @@ def _window(a, origin, n):
     return a[np.ix_(*idx)]
 
 
-@pytest.mark.parametrize("storage,curv,bar", [("f32", "fd", 1e-5), ("f16", "fd", 1e-3), ("f32", "mlp", 1e-5)])
-def test_bubbly_hit_512_sampled_sites(workload, storage, curv, bar):
+@pytest.mark.parametrize("storage,curv,bar,phs", [("f32", "fd", 1e-5, "f64"), ("f16", "fd", 1e-3, "f64"),
+                                                   ("f32", "mlp", 1e-5, "f64"), ("f16", "fd", 1e-3, "fix32")])
+def test_bubbly_hit_512_sampled_sites(workload, storage, curv, bar, phs):
     import torch
 
     import bench
@@ -61,7 +62,8 @@ def test_bubbly_hit_512_sampled_sites(workload, storage, curv, bar):
     shape, phi0, u0, params = workload
     n = shape[0]
     tau = 0.515
-    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, **params)
+    print(f"case 512^3 storage={storage} curv={curv} phi={phs}", flush=True)
+    g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, phi_storage=phs, **params)
     w = None
     if curv == "mlp":
         w = bench.mlp_weights()
@@ -99,7 +101,7 @@ def test_bubbly_hit_512_sampled_sites(workload, storage, curv, bar):
     e_u = np.linalg.norm(gu - ou) / np.linalg.norm(ou)
     e_phi = np.abs(gphi - ophi).max()
     e_p = np.abs(gp - op).max() / np.abs(op).max()
-    print(f"512^3 {storage}/{curv}, {len(pts)} sites after {STEPS} steps: u rel err {e_u:.3e}, "
+    print(f"512^3 {storage}/{curv}/{phs}, {len(pts)} sites after {STEPS} steps: u rel err {e_u:.3e}, "
           f"phi max abs {e_phi:.3e}, p rel max {e_p:.3e}")
     assert e_u < bar
     assert e_phi < (1e-5 if storage == "f32" else 1e-4)
