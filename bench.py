@@ -66,12 +66,14 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def workload(n, seed=0):
+def workload(n, seed=0, diameter=16.0):
+    """The bubbly-HIT recipe on n^3; `diameter` is a number or a (lo, hi)
+    range sampled per bubble (the small-bubble run uses (4, 6))."""
     from paper_2505_01126_amd import inputs as I
 
     shape = (n, n, n)
     nb = max(1, int(round(256 * (n / 512.0) ** 3)))
-    phi0, centers, radii = I.bubble_pack(shape, nb, 16.0, width=4.0, seed=seed)
+    phi0, centers, radii = I.bubble_pack(shape, nb, diameter, width=4.0, seed=seed)
     u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=seed + 1)
     modes = I.forcing_modes(1e-5, seed=seed + 2)
     params = dict(rho_l=1.0, rho_g=0.1, sigma=0.005, mobility=0.05, width=4.0, p0=0.0, modes=modes)
@@ -188,6 +190,104 @@ def batch_leg(steps, warmup, repeats, count=128, seed=3):
             "ms_per_step_batched": ms_batch, "ms_per_step_per_instance": ms_single,
             "mlups_batched": sites / (ms_batch * 1e-3) / 1e6, "mlups_per_instance": sites / (ms_single * 1e-3) / 1e6,
             "speedup": ms_single / ms_batch}
+
+
+def small_bubble_leg(steps, warmup, repeats, n=512):
+    """The same workload with 256 bubbles of d in [4, 6] (seeded): a step costs
+    the same bytes, but far more cells take the learned-curvature branch."""
+    shape, phi0, u0, params, nb = workload(n, seed=0, diameter=(4.0, 6.0))
+    N = shape[0] * shape[1] * shape[2]
+    out = {"bubbles": nb, "diameter": [4.0, 6.0], "interface_cells": int(((phi0 > 0.02) & (phi0 < 0.98)).sum())}
+    for key in ("f32", "f32:mlp", "f16:mlp"):
+        st, curv, phs = parse_variant(key)
+        ms, r0, r1 = time_variant(shape, phi0, u0, params, st, steps, warmup, repeats, 0.515, 0, curv, phs)
+        out[key] = {"ms_per_step": ms, "mlups": N / (ms * 1e-3) / 1e6, "nonfinite": int(r1[9])}
+        print(f"# small bubbles {key}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return out
+
+
+def _spectrum(u):
+    """Shell-summed kinetic energy spectrum E(k), k = 0 .. n/2, of a periodic
+    field u [3, n, n, n] (torch, on the GPU): sum_k E(k) = <|u|^2> / 2."""
+    import torch
+
+    n = u.shape[-1]
+    uh = torch.fft.rfftn(u.double(), dim=(1, 2, 3)) / n ** 3
+    e = 0.5 * (uh.real ** 2 + uh.imag ** 2).sum(0)
+    w = torch.full((n,), 2.0, dtype=torch.float64, device=u.device)[: n // 2 + 1]
+    w[0] = 1.0
+    w[-1] = 1.0  # the Nyquist plane of the half spectrum is not mirrored
+    e = e * w
+    k = torch.fft.fftfreq(n, 1.0 / n).to(u.device)
+    kr = torch.fft.rfftfreq(n, 1.0 / n).to(u.device)
+    kk = torch.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    shell = torch.round(kk).long().clamp(max=n // 2)
+    return torch.zeros(n // 2 + 1, dtype=torch.float64, device=u.device).index_add_(0, shell.flatten(),
+                                                                                     e.flatten())
+
+
+def hit_report(steps=20000, every=2000, n=256, oracle_n=64, oracle_checks=(250, 500, 1000, 2000)):
+    """Forced single-phase HIT (tau 0.55, solenoidal u0 of rms 0.02, forcing
+    on 0 < |k|^2 <= 4): on n^3 for `steps` steps in FP32, FP16 and BF16
+    population storage, the energy spectrum and the velocity difference from
+    the FP32 run every `every` steps; on oracle_n^3, the velocity error of the
+    three storages against the FP64 oracle at `oracle_checks` steps."""
+    import torch
+
+    import oracle as O
+    from paper_2505_01126_amd import inputs as I
+    from paper_2505_01126_amd import lbm
+
+    out = {"n": n, "steps": steps, "tau": 0.55, "storage": {}, "oracle": {"n": oracle_n, "checks": {}}}
+    shape = (n, n, n)
+    u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=1)
+    modes = I.forcing_modes(1e-5, seed=2)
+    ref = {}
+    for st in ("f32", "f16", "bf16"):
+        g = lbm.Lattice(shape, 0.55, u0=u0, modes=modes, p0=1.0, storage=st)
+        rec = out["storage"][st] = {"step": [], "u_rms": [], "rel_diff_vs_f32": [], "spectrum": {}}
+        done = 0
+        while done < steps:
+            g.step(every)
+            done += every
+            u = g.moments()["u"]
+            rms = float(torch.sqrt((u.double() ** 2).sum(0).mean() / 3.0))
+            if st == "f32":
+                ref[done] = u.clone()
+                diff = 0.0
+            else:
+                diff = float(torch.linalg.vector_norm((u - ref[done]).double())
+                             / torch.linalg.vector_norm(ref[done].double()))
+            rec["step"].append(done)
+            rec["u_rms"].append(rms)
+            rec["rel_diff_vs_f32"].append(diff)
+            if done in (every, steps // 2, steps):
+                rec["spectrum"][str(done)] = _spectrum(u).cpu().tolist()
+            print(f"# HIT {n}^3 {st}: {done} steps, u_rms {rms:.5f}, vs f32 {diff:.2e}", file=sys.stderr,
+                  flush=True)
+        g.close()
+    del ref
+    torch.cuda.empty_cache()
+    shape = (oracle_n,) * 3
+    u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=1)
+    o = O.Oracle(shape, 0.55, u0=u0, modes=modes, p0=1.0)
+    gs = {st: lbm.Lattice(shape, 0.55, u0=u0, modes=modes, p0=1.0, storage=st) for st in ("f32", "f16", "bf16")}
+    done = 0
+    for c in oracle_checks:
+        o.step(c - done)
+        for g in gs.values():
+            g.step(c - done)
+        done = c
+        uo = o.moments()["u"]
+        row = {}
+        for st, g in gs.items():
+            u = g.moments()["u"].double().cpu().numpy()
+            row[st] = float(np.linalg.norm(u - uo) / np.linalg.norm(uo))
+        out["oracle"]["checks"][str(c)] = row
+        print(f"# HIT {oracle_n}^3 vs oracle at {c} steps: {row}", file=sys.stderr, flush=True)
+    for g in gs.values():
+        g.close()
+    return out
 
 
 def oracle_timing():
@@ -313,6 +413,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-box ensemble leg")
+    ap.add_argument("--no-small-bubbles", action="store_true", help="skip the d = 4..6 bubble leg")
+    ap.add_argument("--hit-report", action="store_true",
+                    help="only run the forced-HIT storage report (256^3 spectra over 20 000 steps, 64^3 error "
+                         "against the oracle over time) and exit")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle on the four workloads (several minutes of CPU) and exit")
     ap.add_argument("--bandwidth-probe", action="store_true",
@@ -349,6 +453,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.hit_report:
+        print(json.dumps(hit_report()), flush=True)
+        return
     if args.copy_mib > 0:
         print(json.dumps({"copy_mib": args.copy_mib, "copy_gbs": copy_gbs(args.copy_mib)}), flush=True)
         return
@@ -408,6 +515,9 @@ def main():
         bt = line["batch"]
         print(f"# batch: {bt['mlups_batched']:.0f} MLUPS batched vs {bt['mlups_per_instance']:.0f} per instance "
               f"({bt['speedup']:.2f}x), tile {bt['tile']}, z-chunk {bt['zchunk']}", file=sys.stderr, flush=True)
+    if not args.no_small_bubbles:
+        line["small_bubbles"] = small_bubble_leg(min(args.steps, 50), min(args.warmup, 10), args.repeats,
+                                                 args.size)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -8,7 +8,9 @@
   on 0 < |k|^2 <= 4, tau 0.55): 500 steps on 64^3 (the oracle's share of the
   256^3 configuration), FP32, FP16 and BF16 storage;
 * bubbly turbulence (the bench recipe on 64^3: one bubble of d 16, ratio 10,
-  sigma 0.005, tau 0.515, forcing): 500 steps, FP32 and FP16 storage.
+  sigma 0.005, tau 0.515, forcing): 500 steps, FP32 and FP16 storage;
+* Laplace's law over droplet radii R = 8, 12, 16 (64^3, 5000 steps, ratios 1
+  and 10): the fitted surface tension within 5 % of sigma (GPU only).
 
 Bars on the relative L2 error of u: 1e-5 (FP32), 1e-3 (FP16), 1e-2 (BF16,
 8-bit mantissa); phi within 1e-5 (FP32) or 1e-3 (16-bit storage: 500 steps of
@@ -107,3 +109,42 @@ def test_bubbly_turbulence_500_steps(storage):
     m, r = _gpu(shape, 0.515, 500, storage, **kw)
     mo, ro = _oracle("bubbly", shape, 0.515, 500, **kw)
     _check("bubbly turbulence 64^3, 500 steps", m, r, mo, ro, storage, True)
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0])
+def test_laplace_law_fit_over_radii(ratio):
+    """Static droplets of R = 8, 12, 16 on 64^3 (5000 steps each): the least
+    squares fit of the law dp = 2 sigma_eff / R_eff (no offset term: the law
+    has none) gives sigma_eff within 5 % of sigma, and so does every radius on
+    its own; the spurious currents stay small against the capillary velocity.
+    A fit with a free offset is printed too: at R = 16 the droplet fills 6.5 %
+    of the box and the outside pressure is no longer that of an unbounded
+    liquid, which tilts a two-parameter fit more than the law."""
+    from paper_2505_01126_amd import lbm
+
+    shape, sigma = (64, 64, 64), 0.01
+    inv_r, dps, umax = [], [], []
+    for R in (8.0, 12.0, 16.0):
+        phi0, _ = I.droplet(shape, R, 4.0, seed=1)
+        print(f"case Laplace R={R} ratio={ratio}", flush=True)
+        g = lbm.Lattice(shape, 1.0, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=sigma, mobility=0.05,
+                        width=4.0, p0=0.0)
+        g.step(5000)
+        m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+        r = g.reduce()
+        g.close()
+        phi, p = m["phi"], m["p"]
+        reff = (3.0 * phi.sum() / (4.0 * math.pi)) ** (1.0 / 3.0)
+        inv_r.append(1.0 / reff)
+        dps.append(p[phi > 0.99].mean() - p[phi < 0.01].mean())
+        umax.append(r[7])
+    x, y = np.array(inv_r), np.array(dps)
+    sig_eff = (x @ y) / (x @ x) / 2.0
+    each = y / (2.0 * sigma * x)
+    slope, icpt = np.polyfit(x, y, 1)
+    print(f"ratio {ratio}: 1/R_eff {np.round(x, 5).tolist()}, dp {np.round(y, 7).tolist()}, "
+          f"dp / (2 sigma / R_eff) {np.round(each, 4).tolist()}, sigma_eff {sig_eff:.5f} ({sig_eff / sigma - 1:+.2%}); "
+          f"with a free offset: slope / 2 = {slope / 2:.5f}, offset {icpt:.2e}; max |u| {max(umax):.2e}")
+    assert abs(sig_eff / sigma - 1.0) < 0.05
+    assert np.all(np.abs(each - 1.0) < 0.05)
+    assert max(umax) < 1e-2 * sigma / (1.0 / 6.0)
