@@ -436,7 +436,20 @@ struct orc_state {
     double *aext;   /* [3][N] body acceleration */
     double *modes;  /* private copy */
     double *mlp;    /* private copy */
+    double rho_mean; /* box-mean density (constant: sum phi is conserved) */
 };
+
+/* Relaxation time at phase field phi: the kinematic viscosity, affine in tau,
+ * interpolates linearly between the phases, so tau does too; phi is clamped to
+ * [0, 1] so that overshoots of the interface profile stay within the two
+ * phases' values.  Uniform tau when tau_g <= 0 or in single phase. */
+static double tau_at(const orc_params *p, double phi)
+{
+    if (!p->two_phase || p->tau_g <= 0.0)
+        return p->tau;
+    double c = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
+    return c * p->tau + (1.0 - c) * p->tau_g;
+}
 
 /* body acceleration a(x) = sum_m Re(A_m exp(i 2 pi (kx x/nx + ky y/ny + kz z/nz))) of an
  * nx x ny x nz periodic box, evaluated on the window of wx x wy x wz sites whose first
@@ -643,7 +656,7 @@ static void site_curvature(const orc_state *s, long st, const long nb[Q], const 
 }
 
 typedef struct {
-    double pstar, rho, j[3], u[3], acc[3];
+    double pstar, rho, j[3], u[3], acc[3], tau;
 } macro_t;
 
 /* moments, forces and velocity at one site (Sec. 2.2-2.3, Eq. 8) */
@@ -658,9 +671,9 @@ static void site_macro(const orc_state *s, long x, long y, long z, const double 
         for (int a = 0; a < 3; a++)
             j[a] += f[i] * CI[i][a];
     }
-    double rho, g[3] = {0, 0, 0}, K = 0.0, ns[3] = {0, 0, 0};
+    double rho, g[3] = {0, 0, 0}, K = 0.0, ns[3] = {0, 0, 0}, phic = 1.0;
     if (p->two_phase) {
-        double phic = s->phi[st];
+        phic = s->phi[st];
         rho = phic * p->rho_l + (1.0 - phic) * p->rho_g;
         long nb[Q];
         neighbours(p->nx, p->ny, p->nz, x, y, z, nb);
@@ -675,7 +688,8 @@ static void site_macro(const orc_state *s, long x, long y, long z, const double 
         Fs[a] = -1.5 * p->width * p->sigma * K * g2 * ns[a]; /* -(3 delta/2) sigma K |g|^2 n_s */
         grho[a] = (p->rho_l - p->rho_g) * g[a];
         Fp[a] = -pstar * CS2 * grho[a];
-        Fb[a] = rho * s->aext[a * N + st];
+        /* body force, plus buoyancy against the box-mean hydrostatic balance */
+        Fb[a] = rho * s->aext[a * N + st] + (rho - s->rho_mean) * p->gravity[a];
         u0[a] = j[a] + (Fs[a] + Fp[a] + Fb[a]) / (2.0 * rho);
     }
     /* viscous correction with the non-equilibrium stress at u0 */
@@ -688,12 +702,13 @@ static void site_macro(const orc_state *s, long x, long y, long z, const double 
                 sum += (f[i] - feq0[i]) * CI[i][a] * CI[i][b];
             P[a][b] = sum;
         }
-    double nu = CS2 * (p->tau - 0.5);
+    double tau = tau_at(p, phic);
+    double nu = CS2 * (tau - 0.5);
     for (int a = 0; a < 3; a++) {
         double Fnu = 0.0;
         for (int b = 0; b < 3; b++)
             Fnu += P[a][b] * grho[b];
-        Fnu *= -(nu / (p->tau * CS2));
+        Fnu *= -(nu / (tau * CS2));
         double F = Fs[a] + Fp[a] + Fb[a] + Fnu;
         m->acc[a] = F / rho;
         m->j[a] = j[a];
@@ -701,12 +716,13 @@ static void site_macro(const orc_state *s, long x, long y, long z, const double 
     }
     m->pstar = pstar;
     m->rho = rho;
+    m->tau = tau;
 }
 
 orc_state *orc_create(const orc_params *p, const double *phi0, const double *u0, const double *pstar0)
 {
     lattice_init();
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->tau <= 0.5)
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->tau <= 0.5 || (p->tau_g > 0.0 && p->tau_g <= 0.5))
         return NULL;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     s->p = *p;
@@ -731,6 +747,14 @@ orc_state *orc_create(const orc_params *p, const double *phi0, const double *u0,
     s->p.mlp = s->mlp;
     if (phi0 && p->two_phase)
         memcpy(s->phi, phi0, sizeof(double) * N);
+    if (p->two_phase) {
+        double sum = 0.0;
+        for (long i = 0; i < N; i++)
+            sum += s->phi[i];
+        s->rho_mean = p->rho_g + (p->rho_l - p->rho_g) * (sum / (double)N);
+    } else {
+        s->rho_mean = p->rho_l;
+    }
     if (u0)
         memcpy(s->uprev, u0, sizeof(double) * 3 * N);
     eval_forcing(s);
@@ -750,7 +774,7 @@ orc_state *orc_create(const orc_params *p, const double *phi0, const double *u0,
                 double A[3][3];
                 for (int a = 0; a < 3; a++)
                     for (int b = 0; b < 3; b++)
-                        A[a][b] = -CS2 * p->tau * (G[a][b] + G[b][a]);
+                        A[a][b] = -CS2 * tau_at(p, s->phi[st]) * (G[a][b] + G[b][a]);
                 double ps = pstar0 ? pstar0[st] : p->p0;
                 orc_feq(ps, u, feq);
                 for (int i = 0; i < Q; i++) {
@@ -797,7 +821,7 @@ void orc_step(orc_state *s, long nsteps)
                     for (int i = 0; i < Q; i++)
                         f[i] = s->f[i * N + st];
                     site_macro(s, x, y, z, f, &m);
-                    orc_collide(f, m.u, m.acc, p->tau, fp, NULL);
+                    orc_collide(f, m.u, m.acc, m.tau, fp, NULL);
                     for (int i = 0; i < Q; i++)
                         s->fpost[i * N + st] = fp[i];
                     for (int a = 0; a < 3; a++)

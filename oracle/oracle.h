@@ -36,6 +36,8 @@ typedef struct {
     int curv_mode;          /* 0 = finite-difference curvature, 1 = MLP blend */
     double k_lo, k_hi;      /* blend ramp on |K_FD| for curv_mode = 1 */
     const double *mlp;      /* ORC_MLP_NPARAM weights (values already fp16-exact) */
+    double gravity[3];      /* buoyancy acceleration g: force (rho - rho_mean) g, rho_mean the box mean */
+    double tau_g;           /* relaxation time of the phi = 0 phase (<= 0: tau); tau(phi) interpolates */
 } orc_params;
 
 typedef struct orc_state orc_state;
