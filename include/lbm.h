@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 #define LBM_NRED 10          /* number of lbm_reduce outputs */
 #define LBM_MAX_MODES 64     /* forcing table rows */
 #define LBM_MLP_NPARAM 6212  /* 27*64+64 + 64*64+64 + 64*4+4 */
@@ -89,6 +89,16 @@ typedef struct {
     double mlp_k_hi;
     int32_t phi_storage; /* LBM_PHI_* (ignored in single phase) */
     int32_t reserved;    /* 0 */
+    /* Two-phase only (ignored in single phase).  Buoyancy: body force
+     * (rho - rho_mean) g, rho_mean the box-mean density (constant, since
+     * sum phi is conserved), so a periodic box with gravity does not accelerate
+     * as a whole; with g != 0, lbm_init measures rho_mean on the device and
+     * waits for the stream.  Viscosity contrast: tau_g > 1/2 is the relaxation
+     * time of the phi = 0 phase and tau(phi) = phi tau + (1 - phi) tau_g with
+     * phi clamped to [0, 1] (the kinematic viscosity interpolates linearly);
+     * tau_g = 0 keeps one tau. */
+    double gravity[3];   /* g (x, y, z), lattice units */
+    double tau_g;
 } lbm_config;
 
 /* LBM_ABI_VERSION of the loaded library. */

@@ -88,6 +88,9 @@ const char *validate(const lbm_config *c)
         if (!std::isfinite(c->sigma)) return "sigma must be finite";
     }
     if (!std::isfinite(c->p0)) return "p0 must be finite";
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(c->gravity[a])) return "gravity must be finite";
+    if (c->tau_g != 0.0 && !(c->tau_g > 0.5 && std::isfinite(c->tau_g))) return "tau_g must be 0 or > 1/2";
     if (c->n_modes < 0 || c->n_modes > LBM_MAX_MODES) return "n_modes out of range";
     if (c->n_modes > 0 && !c->modes) return "modes is NULL";
     for (int m = 0; m < c->n_modes; m++) {
@@ -245,6 +248,11 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
     }
     P.k_lo = (float)lo;
     P.k_hi = (float)hi;
+    P.gravity_on = cfg->two_phase && (cfg->gravity[0] != 0.0 || cfg->gravity[1] != 0.0 || cfg->gravity[2] != 0.0);
+    for (int a = 0; a < 3; a++) P.grav[a] = P.gravity_on ? (float)cfg->gravity[a] : 0.0f;
+    P.rho_mean = P.rho_l;
+    P.tau_l = (float)cfg->tau;
+    P.tau_g = cfg->two_phase && cfg->tau_g > 0.0 ? (float)cfg->tau_g : 0.0f;
     P.mlp = h->ws + L.mlp;
     P.frow = nullptr;
     P.fx = nullptr;
@@ -327,6 +335,23 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
         P.fx = dx;
     }
     hipError_t e = lbm::launch_init(P, cfg->storage, h->f(0), h->phi(0), h->u(0), d_phi0, d_u0, d_pstar0, h->stream);
+    if (e == hipSuccess && P.gravity_on) {
+        // box-mean density from sum phi of the initial state (finite-difference
+        // curvature for this reduction: the network weights are not set yet)
+        lbm::Params Pr = P;
+        Pr.curv_mode = LBM_CURV_FD;
+        double red[LBM_NRED];
+        double *dred = (double *)(h->ws + L.red);
+        e = lbm::launch_reduce(Pr, cfg->storage, h->f(0), h->phi(0), (double *)(h->ws + L.partials), dred,
+                               h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(red, dred, sizeof(double) * LBM_NRED, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) {
+            const double N = (double)cfg->nx * cfg->ny * cfg->nz;
+            P.rho_mean = (float)(cfg->rho_g + (cfg->rho_l - cfg->rho_g) * (red[0] / N));
+        }
+    }
     if (e != hipSuccess) {
         g_init_err = std::string("init kernel: ") + hipGetErrorString(e);
         delete h;

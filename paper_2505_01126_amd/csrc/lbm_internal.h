@@ -50,6 +50,12 @@ struct Params {
     float d6;       // 6 D     (diffusion link coefficient, times w_i)
     float k3;       // 3 kappa (sharpening link coefficient, times w_i)
     float k_lo, k_hi;
+    // buoyancy (rho - rho_mean) g when gravity_on; phase-dependent relaxation
+    // time tau(phi) = phi tau_l + (1 - phi) tau_g (phi clamped to [0, 1]) when tau_g > 0
+    int gravity_on;
+    float rho_mean;
+    float grav[3];
+    float tau_l, tau_g;
     const float *frow;       // device forcing row table, or nullptr
     const float4 *fx;        // device forcing x twiddles, or nullptr
     const void *mlp;         // device fp16 weights, or nullptr

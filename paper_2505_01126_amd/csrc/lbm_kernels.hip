@@ -199,6 +199,7 @@ struct Macro {
     float u[3];   // u = j + a/2
     float a[3];   // F / rho
     float S[6];   // Pi - p* c_s^2 I  (xx yy zz xy xz yz)
+    float omega;  // 1 / tau at this site
 };
 
 // Phase-field stencil quantities at a site: g = grad phi, H = Hessian (lattice
@@ -320,13 +321,25 @@ __device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const
         const float inv_rho = __builtin_amdgcn_rcpf(rho);
         float F[3], u0[3];
 #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            F[a] = fs[a] + cp * g[a] + rho * aext[a];
-            u0[a] = j[a] + 0.5f * F[a] * inv_rho;
+        for (int a = 0; a < 3; a++) F[a] = fs[a] + cp * g[a] + rho * aext[a];
+        if (P.gravity_on) {  // buoyancy against the box-mean hydrostatic balance
+            const float dr = rho - P.rho_mean;
+#pragma unroll
+            for (int a = 0; a < 3; a++) F[a] += dr * P.grav[a];
         }
+#pragma unroll
+        for (int a = 0; a < 3; a++) u0[a] = j[a] + 0.5f * F[a] * inv_rho;
+        // relaxation rate and viscous-correction coefficient nu / (tau c_s^2) = 1 - omega / 2
+        float omega = P.omega, fnu = P.fnu_coef;
+        if (P.tau_g > 0.0f) {
+            const float c = fminf(fmaxf(G.phi, 0.0f), 1.0f);
+            omega = 1.0f / fmaf(c, P.tau_l - P.tau_g, P.tau_g);
+            fnu = 1.0f - 0.5f * omega;
+        }
+        m.omega = omega;
         const float n0 = m.S[0] - u0[0] * u0[0], n1 = m.S[1] - u0[1] * u0[1], n2 = m.S[2] - u0[2] * u0[2];
         const float n3 = m.S[3] - u0[0] * u0[1], n4 = m.S[4] - u0[0] * u0[2], n5 = m.S[5] - u0[1] * u0[2];
-        const float cnu = -P.fnu_coef * drho;
+        const float cnu = -fnu * drho;
         F[0] += cnu * (n0 * g[0] + n3 * g[1] + n4 * g[2]);
         F[1] += cnu * (n3 * g[0] + n1 * g[1] + n5 * g[2]);
         F[2] += cnu * (n4 * g[0] + n5 * g[1] + n2 * g[2]);
@@ -343,6 +356,7 @@ __device__ __forceinline__ void site_macro(const M10 &M, const PhiGrad &G, const
             m.u[a] = j[a] + 0.5f * aext[a];
         }
         m.rho = P.rho_l;
+        m.omega = P.omega;
     }
 }
 
@@ -861,7 +875,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 
             // regularised collision, written to this site's own slots
             float h[27];
-            collide(m, P.omega, h);
+            collide(m, m.omega, h);
             const __amdgpu_buffer_rsrc_t dst = plane_rsrc(fout + (size_t)z * pstride, pbytes);
             uint32_t soff = 0;
 #pragma unroll
@@ -943,7 +957,11 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, void *
             }
         }
     }
-    const double tau = 1.0 / (double)P.omega;
+    double tau = 1.0 / (double)P.omega;
+    if (P.two_phase && P.tau_g > 0.0f) {  // relaxation time of the initial phase field
+        const double c = fmin(fmax(phi0[s], 0.0), 1.0);
+        tau = c * (double)P.tau_l + (1.0 - c) * (double)P.tau_g;
+    }
     double A[3][3];
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) A[a][b] = -(tau / 3.0) * (G[a][b] + G[b][a]);

@@ -32,7 +32,7 @@ def test_abi_version_and_constants():
     assert lbm.lbm_abi_version() == ver
     assert int(re.search(r"#define LBM_NRED (\d+)", text).group(1)) == lbm.NRED
     assert int(re.search(r"#define LBM_MLP_NPARAM (\d+)", text).group(1)) == lbm.MLP_NPARAM
-    assert C.sizeof(lbm.lbm_config) == 120
+    assert C.sizeof(lbm.lbm_config) == 152
 
 
 def test_config_struct_matches_header(tmp_path):
@@ -72,7 +72,9 @@ def test_workspace_bytes_counts_state():
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.8, shape=(4, 64, 64)),
                                 dict(tau=0.8, shape=(8, 4097, 4097)),
                                 dict(tau=0.8, storage="f16", modes=[[3, 0, 0] + [0] * 6]),
-                                dict(tau=0.8, two_phase=True, phi_storage=2)])
+                                dict(tau=0.8, two_phase=True, phi_storage=2),
+                                dict(tau=0.8, two_phase=True, tau_g=0.45),
+                                dict(tau=0.8, two_phase=True, gravity=(0.0, float("nan"), 0.0))])
 def test_invalid_configs_rejected_on_host(kw):
     shape = kw.pop("shape", (16, 16, 16))
     tau = kw.pop("tau")
