@@ -431,6 +431,7 @@ struct orc_state {
     double *fpost;  /* [27][N] scratch */
     double *phi;    /* [N] */
     double *phinew; /* [N] */
+    double *stage;  /* [N] Runge-Kutta stage (ac_rk3) */
     double *uprev;  /* [3][N] velocity of the previous step (Allen-Cahn advection) */
     double *unew;   /* [3][N] */
     double *aext;   /* [3][N] body acceleration */
@@ -732,6 +733,7 @@ orc_state *orc_create(const orc_params *p, const double *phi0, const double *u0,
     s->fpost = (double *)malloc(sizeof(double) * Q * N);
     s->phi = (double *)calloc(N, sizeof(double));
     s->phinew = (double *)calloc(N, sizeof(double));
+    s->stage = (double *)calloc(N, sizeof(double));
     s->uprev = (double *)calloc(3 * N, sizeof(double));
     s->unew = (double *)calloc(3 * N, sizeof(double));
     s->aext = (double *)calloc(3 * N, sizeof(double));
@@ -796,6 +798,7 @@ void orc_destroy(orc_state *s)
     free(s->fpost);
     free(s->phi);
     free(s->phinew);
+    free(s->stage);
     free(s->uprev);
     free(s->unew);
     free(s->aext);
@@ -829,7 +832,24 @@ void orc_step(orc_state *s, long nsteps)
                 }
         /* 2. Allen-Cahn update with the velocity of the previous step */
         if (p->two_phase)
-            orc_ac_update(nx, ny, nz, s->phi, s->uprev, p->mobility, p->width, s->phinew);
+        {
+            if (p->ac_rk3) {
+                /* three-stage strong-stability-preserving Runge-Kutta (Shu & Osher),
+                 * each stage an Euler step of the same right-hand side with the
+                 * velocity held at u^(n-1):
+                 *   phi1 = phi + L(phi),  phi2 = 3/4 phi + 1/4 (phi1 + L(phi1)),
+                 *   phi^{n+1} = 1/3 phi + 2/3 (phi2 + L(phi2)) */
+                orc_ac_update(nx, ny, nz, s->phi, s->uprev, p->mobility, p->width, s->phinew);
+                orc_ac_update(nx, ny, nz, s->phinew, s->uprev, p->mobility, p->width, s->stage);
+                for (long i = 0; i < N; i++)
+                    s->stage[i] = 0.75 * s->phi[i] + 0.25 * s->stage[i];
+                orc_ac_update(nx, ny, nz, s->stage, s->uprev, p->mobility, p->width, s->phinew);
+                for (long i = 0; i < N; i++)
+                    s->phinew[i] = s->phi[i] / 3.0 + (2.0 / 3.0) * s->phinew[i];
+            } else {
+                orc_ac_update(nx, ny, nz, s->phi, s->uprev, p->mobility, p->width, s->phinew);
+            }
+        }
         /* 3. streaming: f_i(x, n+1) = f^post_i(x - c_i, n) */
 #pragma omp parallel for
         for (long z = 0; z < nz; z++)

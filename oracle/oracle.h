@@ -38,6 +38,7 @@ typedef struct {
     const double *mlp;      /* ORC_MLP_NPARAM weights (values already fp16-exact) */
     double gravity[3];      /* buoyancy acceleration g: force (rho - rho_mean) g, rho_mean the box mean */
     double tau_g;           /* relaxation time of the phi = 0 phase (<= 0: tau); tau(phi) interpolates */
+    int ac_rk3;             /* Allen-Cahn time integration: 0 explicit Euler, 1 three-stage SSP Runge-Kutta */
 } orc_params;
 
 typedef struct orc_state orc_state;

@@ -26,7 +26,7 @@ class _Params(C.Structure):
         ("p0", C.c_double), ("n_modes", C.c_int), ("modes", C.POINTER(C.c_double)),
         ("curv_mode", C.c_int), ("k_lo", C.c_double), ("k_hi", C.c_double),
         ("mlp", C.POINTER(C.c_double)),
-        ("gravity", C.c_double * 3), ("tau_g", C.c_double),
+        ("gravity", C.c_double * 3), ("tau_g", C.c_double), ("ac_rk3", C.c_int),
     ]
 
 
@@ -221,7 +221,7 @@ class Oracle:
 
     def __init__(self, shape, tau, phi0=None, u0=None, pstar0=None, two_phase=None, rho_l=1.0, rho_g=1.0,
                  sigma=0.0, mobility=0.0, width=4.0, p0=1.0, modes=None, curv_mode=0, k_lo=0.4, k_hi=0.6,
-                 mlp=None, gravity=(0.0, 0.0, 0.0), tau_g=0.0):
+                 mlp=None, gravity=(0.0, 0.0, 0.0), tau_g=0.0, ac_rk3=False):
         nz, ny, nx = shape
         self.shape = tuple(shape)
         self.N = nx * ny * nz
@@ -231,7 +231,7 @@ class Oracle:
         self._mlp = _f64(mlp) if mlp is not None else None
         prm = _Params(nx, ny, nz, int(two_phase), tau, rho_l, rho_g, sigma, mobility, width, p0,
                       0 if modes is None else len(self._modes), _p(self._modes), int(curv_mode), k_lo, k_hi,
-                      _p(self._mlp), (C.c_double * 3)(*[float(v) for v in gravity]), float(tau_g))
+                      _p(self._mlp), (C.c_double * 3)(*[float(v) for v in gravity]), float(tau_g), int(ac_rk3))
         self._phi0 = _f64(phi0)
         self._u0 = _f64(u0)
         self._ps0 = _f64(pstar0)
