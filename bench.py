@@ -9,9 +9,11 @@ the paper's benchmark viscosity), large-scale forcing on the shells
 rms 0.02.  Populations stored in FP32 (the reported value) and in FP16 / BF16
 (reported beside it); arithmetic is FP32 in every variant.  The phase field
 is stored in FP64, or in int32 fixed point in the ":fix32" variants (4 bytes
-less read and written per site).
+less read and written per site).  The ":rk3" variants advance the phase field
+with three Runge-Kutta stages: the step kernel's own update is the first, two
+phase-field launches per step add the others.
 
-A step is one fused kernel launch over the whole box.  Inputs are resident in
+A step is one fused kernel launch over the whole box (three launches with ":rk3").  Inputs are resident in
 HBM before timing starts; W untimed warm-up steps, then R blocks of K timed
 steps, each between two stream synchronisations and timed with HIP events on
 the launch stream; the median block is reported.  The learned-curvature
@@ -41,20 +43,29 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # phi FP64 read + write, u FP32 x3 read + write (the advecting velocity)
 BYTES_PER_LUP = {"f32": 27 * 4 * 2 + 8 + 8 + 12 + 12, "f16": 27 * 2 * 2 + 40, "bf16": 27 * 2 * 2 + 40}
 PHI_BYTES_SAVED = {"f64": 0, "fix32": 4 + 4}  # int32 phi: 4 B read + 4 B written instead of 8 + 8
+# each extra Runge-Kutta stage of phi: stage input and phi^n read, stage output
+# written (FP64), the three face velocities read
+RK3_STAGE_BYTES = 8 + 8 + 8 + 12
 
 
 def parse_variant(key):
-    """'storage[:curvature][:phi storage]' -> (storage, curvature, phi storage)."""
+    """'storage[:curvature][:phi storage][:rk3]' -> (storage, curvature, phi storage, rk3)."""
     parts = key.split(":")
-    st, curv, phs = parts[0], "fd", "f64"
+    st, curv, phs, rk3 = parts[0], "fd", "f64", False
     for p in parts[1:]:
         if p in ("fd", "mlp"):
             curv = p
         elif p in PHI_BYTES_SAVED:
             phs = p
+        elif p == "rk3":
+            rk3 = True
         else:
             raise SystemExit(f"bench.py: unknown variant field {p!r} in {key!r}")
-    return st, curv, phs
+    return st, curv, phs, rk3
+
+
+def bytes_per_lup(st, phs="f64", rk3=False):
+    return BYTES_PER_LUP[st] - PHI_BYTES_SAVED[phs] + (2 * RK3_STAGE_BYTES if rk3 else 0)
 KERNEL_SOURCES = ["paper_2505_01126_amd/csrc/lbm_kernels.hip", "paper_2505_01126_amd/csrc/lbm_internal.h"]
 
 
@@ -104,13 +115,14 @@ def mlp_weights(seed=5):
     return w.astype(np.float16).astype(np.float64)
 
 
-def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, zchunk, curv="fd", phs="f64"):
+def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, zchunk, curv="fd", phs="f64",
+                 rk3=False):
     import torch
 
     from paper_2505_01126_amd import lbm
 
     g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, curv_mode=curv, phi_storage=phs,
-                    **params)
+                    ac_rk3=rk3, **params)
     if curv == "mlp":
         g.set_mlp(torch.tensor(mlp_weights().astype(np.float16).view(np.int16), device="cuda"))
     r0 = g.reduce()
@@ -199,8 +211,8 @@ def small_bubble_leg(steps, warmup, repeats, n=512):
     N = shape[0] * shape[1] * shape[2]
     out = {"bubbles": nb, "diameter": [4.0, 6.0], "interface_cells": int(((phi0 > 0.02) & (phi0 < 0.98)).sum())}
     for key in ("f32", "f32:mlp", "f16:mlp"):
-        st, curv, phs = parse_variant(key)
-        ms, r0, r1 = time_variant(shape, phi0, u0, params, st, steps, warmup, repeats, 0.515, 0, curv, phs)
+        st, curv, phs, rk3 = parse_variant(key)
+        ms, r0, r1 = time_variant(shape, phi0, u0, params, st, steps, warmup, repeats, 0.515, 0, curv, phs, rk3)
         out[key] = {"ms_per_step": ms, "mlups": N / (ms * 1e-3) / 1e6, "nonfinite": int(r1[9])}
         print(f"# small bubbles {key}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
     return out
@@ -349,7 +361,7 @@ def copy_gbs(mib=1024, reps=10):
     return 2 * (mib << 20) / dt / 1e9
 
 
-def error_vs_oracle(storage, curv, phs="f64", steps=50, n=64):
+def error_vs_oracle(storage, curv, phs="f64", rk3=False, steps=50, n=64):
     """Relative L2 error of u (and max |phi| difference) against the FP64
     oracle after `steps` steps on an n^3 box of the bench recipe."""
     import oracle as O
@@ -357,7 +369,8 @@ def error_vs_oracle(storage, curv, phs="f64", steps=50, n=64):
     import torch
 
     shape, phi0, u0, params, nb = workload(n, seed=0)
-    g = lbm.Lattice(shape, 0.515, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, phi_storage=phs, **params)
+    g = lbm.Lattice(shape, 0.515, phi0=phi0, u0=u0, storage=storage, curv_mode=curv, phi_storage=phs, ac_rk3=rk3,
+                    **params)
     w = None
     if curv == "mlp":
         w = mlp_weights()
@@ -365,7 +378,7 @@ def error_vs_oracle(storage, curv, phs="f64", steps=50, n=64):
     g.step(steps)
     m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
     g.close()
-    o = O.Oracle(shape, 0.515, phi0=phi0, u0=u0, curv_mode=1 if curv == "mlp" else 0, mlp=w, **params)
+    o = O.Oracle(shape, 0.515, phi0=phi0, u0=u0, curv_mode=1 if curv == "mlp" else 0, mlp=w, ac_rk3=rk3, **params)
     o.step(steps)
     mo = o.moments()
     return {"u_rel_l2": float(np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])),
@@ -406,9 +419,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--repeats", type=int, default=5)
-    ap.add_argument("--storage", default="f32,f16,bf16,f32:mlp,f16:mlp,f32:fix32,f16:fix32",
-                    help="comma list of storage[:curvature][:phi storage] variants (curvature fd|mlp, phi "
-                         "f64|fix32); the first is the reported value")
+    ap.add_argument("--storage", default="f32,f16,bf16,f32:mlp,f16:mlp,f32:fix32,f16:fix32,f32:rk3,f16:rk3",
+                    help="comma list of storage[:curvature][:phi storage][:rk3] variants (curvature fd|mlp, phi "
+                         "f64|fix32, rk3: Runge-Kutta phase field); the first is the reported value")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -468,26 +481,28 @@ def main():
     name = f"bubbly_hit_{args.size}"
     variants = {}
     for key in [s.strip() for s in args.storage.split(",") if s.strip()]:
-        st, curv, phs = parse_variant(key)
+        st, curv, phs, rk3 = parse_variant(key)
         ms, r0, r1 = time_variant(shape, phi0, u0, params, st, args.steps, args.warmup, args.repeats, tau,
-                                  args.zchunk, curv, phs)
+                                  args.zchunk, curv, phs, rk3)
         mlups = N / (ms * 1e-3) / 1e6
-        blup = BYTES_PER_LUP[st] - PHI_BYTES_SAVED[phs]
+        blup = bytes_per_lup(st, phs, rk3)
         achieved = blup * N / (ms * 1e-3) / 1e9
         variants[key] = {
-            "storage": st, "curvature": curv, "phi_storage": phs, "mlups": mlups, "ms_per_step": ms,
+            "storage": st, "curvature": curv, "phi_storage": phs, "phase_field_integrator": "rk3" if rk3 else "euler",
+            "mlups": mlups, "ms_per_step": ms,
             "bytes_per_lup": blup, "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS,
             "phase_volume_drift": abs(r1[0] - r0[0]) / r0[0], "nonfinite": int(r1[9]), "max_u": r1[7],
         }
         print(f"# {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%})",
               file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:  # the oracle runs on the host: skipped with it
-            variants[key]["error_vs_oracle"] = error_vs_oracle(st, curv, phs)
+            variants[key]["error_vs_oracle"] = error_vs_oracle(st, curv, phs, rk3)
             print(f"#   vs FP64 oracle (64^3, 50 steps): u {variants[key]['error_vs_oracle']['u_rel_l2']:.2e}",
                   file=sys.stderr, flush=True)
     primary = next(iter(variants))
     v = variants[primary]
-    traffic = traffic_for(name, v["storage"]) if (v["curvature"], v["phi_storage"]) == ("fd", "f64") else None
+    traffic = (traffic_for(name, v["storage"])
+               if (v["curvature"], v["phi_storage"], v["phase_field_integrator"]) == ("fd", "f64", "euler") else None)
     line = {
         "metric": "MLUPS & % HBM roofline, 512^3 bubbly HIT, FP32 vs FP16-stored populations",
         "value": v["mlups"],

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3
+#define LBM_ABI_VERSION 4
 #define LBM_NRED 10          /* number of lbm_reduce outputs */
 #define LBM_MAX_MODES 64     /* forcing table rows */
 #define LBM_MLP_NPARAM 6212  /* 27*64+64 + 64*64+64 + 64*4+4 */
@@ -99,6 +99,14 @@ typedef struct {
      * tau_g = 0 keeps one tau. */
     double gravity[3];   /* g (x, y, z), lattice units */
     double tau_g;
+    /* Time integration of the phase field (two-phase only): 0 explicit Euler,
+     * one update per step inside the step kernel; 1 three-stage strong-
+     * stability-preserving Runge-Kutta (Shu-Osher) with the velocity held at
+     * the previous step's: the step kernel's Euler update is the first stage
+     * and two more launches per step add the others (needs phi_storage F64;
+     * 2 x 8 bytes per site more workspace). */
+    int32_t ac_rk3;
+    int32_t reserved2;   /* 0 */
 } lbm_config;
 
 /* LBM_ABI_VERSION of the loaded library. */

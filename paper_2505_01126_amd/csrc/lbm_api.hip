@@ -27,7 +27,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
+    size_t f[2], phi[2], u[2], stage[2], frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -50,6 +50,12 @@ Layout layout_of(const lbm_config &c)
         L.u[1] = take(12 * N);
     } else {
         L.phi[0] = L.phi[1] = L.u[0] = L.u[1] = (size_t)-1;
+    }
+    if (c.two_phase && c.ac_rk3) {  // the two intermediate Runge-Kutta stages of phi
+        L.stage[0] = take(8 * N);
+        L.stage[1] = take(8 * N);
+    } else {
+        L.stage[0] = L.stage[1] = (size_t)-1;
     }
     if (c.n_modes > 0) {
         L.frow = take(sizeof(float) * lbm::FROW * (size_t)c.ny * c.nz);
@@ -79,6 +85,9 @@ const char *validate(const lbm_config *c)
     if (c->curv_mode != LBM_CURV_FD && c->curv_mode != LBM_CURV_MLP) return "curv_mode must be FD or MLP";
     if (c->curv_mode == LBM_CURV_MLP && !c->two_phase) return "MLP curvature needs two_phase";
     if (c->phi_storage != LBM_PHI_F64 && c->phi_storage != LBM_PHI_FIX32) return "phi_storage must be F64 or FIX32";
+    if (c->ac_rk3 != 0 && c->ac_rk3 != 1) return "ac_rk3 must be 0 or 1";
+    if (c->ac_rk3 && c->two_phase && c->phi_storage == LBM_PHI_FIX32)
+        return "the Runge-Kutta phase-field update needs phi_storage F64";
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return "tau must be > 1/2";
     if (!(c->rho_l > 0.0) || !std::isfinite(c->rho_l)) return "rho_l must be > 0";
     if (c->two_phase) {
@@ -124,7 +133,8 @@ struct lbm_batch {
     char *table = nullptr;
     size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
     int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
-    bool tp = false, frc = false, ml = false, fix = false, dirty = true;
+    bool tp = false, frc = false, ml = false, fix = false, rk3 = false, dirty = true;
+    int grid_ac = 0;  // persistent grid of the Runge-Kutta stage kernel
     hipGraphExec_t exec = nullptr;
     std::string err;
 
@@ -140,7 +150,12 @@ struct lbm_batch {
         return LBM_EHIP;
     }
     lbm::Params *d_tab() { return (lbm::Params *)(table + off_tab); }
-    lbm::Buffers *d_buf() { return (lbm::Buffers *)(table + off_buf); }
+    // buffer tables [kind][parity][member]: kind 0 the step, 1 and 2 the
+    // second and third Runge-Kutta stages of phi
+    lbm::Buffers *d_buf(int kind = 0, int parity = 0)
+    {
+        return (lbm::Buffers *)(table + off_buf) + (size_t)(2 * kind + parity) * m.size();
+    }
     uint32_t *d_first() { return (uint32_t *)(table + off_first); }
     uint32_t *d_counter() { return (uint32_t *)(table + off_counter); }
     void drop_graph()
@@ -165,6 +180,7 @@ struct lbm_handle {
 
     void *f(int k) { return ws + L.f[k]; }
     void *phi(int k) { return cfg.two_phase ? (void *)(ws + L.phi[k]) : nullptr; }
+    void *stage(int k) { return cfg.two_phase && cfg.ac_rk3 ? (void *)(ws + L.stage[k]) : nullptr; }
     float *u(int k) { return cfg.two_phase ? (float *)(ws + L.u[k]) : nullptr; }
 
     int fail(int code, const std::string &msg)
@@ -544,11 +560,11 @@ BatchOffsets batch_offsets(int n)
     o.tab = off;
     off = align_up(off + sizeof(lbm::Params) * (size_t)n);
     o.buf = off;
-    off = align_up(off + sizeof(lbm::Buffers) * 2 * (size_t)n);
+    off = align_up(off + sizeof(lbm::Buffers) * 3 * 2 * (size_t)n);
     o.first = off;
     off = align_up(off + sizeof(uint32_t) * ((size_t)n + 1));
     o.counter = off;
-    off = align_up(off + sizeof(uint32_t) * 2);
+    off = align_up(off + sizeof(uint32_t) * 3 * 2);  // one pair of queue counters per kernel kind
     o.total = off;
     return o;
 }
@@ -570,23 +586,33 @@ void set_tiling(lbm::Params &P, int tile, int zc)
 int batch_upload(lbm_batch *b)
 {
     const int n = (int)b->m.size();
-    std::vector<lbm::Buffers> buf(2 * (size_t)n);
+    std::vector<lbm::Buffers> buf(3 * 2 * (size_t)n, lbm::Buffers{});
     std::vector<uint32_t> first((size_t)n + 1, 0u);
     for (int i = 0; i < n; i++) {
         lbm_handle *h = b->m[i];
         b->cur0[i] = h->cur;
         for (int p = 0; p < 2; p++) {
             const int c = h->cur ^ p, o = c ^ 1;
-            buf[(size_t)p * n + i] = lbm::Buffers{h->f(c), h->f(o), h->phi(c), h->phi(o), h->u(c), h->u(o)};
+            // with the Runge-Kutta update the step's own Euler update of phi
+            // is the first stage (into stage 0); stages 2 and 3 follow
+            buf[(size_t)p * n + i] = lbm::Buffers{h->f(c), h->f(o), h->phi(c), b->rk3 ? h->stage(0) : h->phi(o),
+                                                  h->u(c), h->u(o), nullptr};
+            if (b->rk3) {
+                buf[(size_t)(2 + p) * n + i] =
+                    lbm::Buffers{nullptr, nullptr, h->stage(0), h->stage(1), h->u(c), nullptr, h->phi(c)};
+                buf[(size_t)(4 + p) * n + i] =
+                    lbm::Buffers{nullptr, nullptr, h->stage(1), h->phi(o), h->u(c), nullptr, h->phi(c)};
+            }
         }
         first[i + 1] = first[i] + (uint32_t)b->P[i].nblocks;
     }
-    // both queue counters start at zero (each launch clears the other one)
-    hipError_t e = hipMemsetAsync(b->d_counter(), 0, 2 * sizeof(uint32_t), b->stream);
+    // all queue counters start at zero (each launch clears the other one of its pair)
+    hipError_t e = hipMemsetAsync(b->d_counter(), 0, 3 * 2 * sizeof(uint32_t), b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_tab(), b->P.data(), sizeof(lbm::Params) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_buf(), buf.data(), sizeof(lbm::Buffers) * 2 * n, hipMemcpyHostToDevice, b->stream);
+        e = hipMemcpyAsync(b->d_buf(), buf.data(), sizeof(lbm::Buffers) * 3 * 2 * n, hipMemcpyHostToDevice,
+                           b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_first(), first.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // host staging is released below
@@ -597,12 +623,21 @@ int batch_upload(lbm_batch *b)
     return LBM_OK;
 }
 
-// one launch of the batch kernel with the given parity of the buffer table
+// one time step of the batch with the given parity of the buffer tables: the
+// step kernel, then, with the Runge-Kutta phase-field update, its second and
+// third stages (Shu-Osher coefficients 3/4, 1/4 and 1/3, 2/3)
 hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
 {
     const int n = (int)b->m.size();
-    return lbm::launch_step_batch(b->d_tab(), b->d_buf() + (size_t)parity * n, b->d_first(), n, b->d_counter(),
-                                  parity, b->storage, b->tp, b->frc, b->ml, b->fix, b->tile, b->grid, s);
+    hipError_t e = lbm::launch_step_batch(b->d_tab(), b->d_buf(0, parity), b->d_first(), n, b->d_counter(), parity,
+                                          b->storage, b->tp, b->frc, b->ml, b->fix, b->tile, b->grid, s);
+    if (e == hipSuccess && b->rk3)
+        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(1, parity), b->d_first(), n, b->d_counter() + 2, parity,
+                                       0.75, 0.25, b->tile, b->grid_ac, s);
+    if (e == hipSuccess && b->rk3)
+        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(2, parity), b->d_first(), n, b->d_counter() + 4, parity,
+                                       1.0 / 3.0, 2.0 / 3.0, b->tile, b->grid_ac, s);
+    return e;
 }
 
 void batch_advance(lbm_batch *b, int64_t k)
@@ -651,8 +686,9 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
         if (!h) return bad(LBM_EINVAL, "NULL member");
         if (h->cfg.storage != h0->cfg.storage || h->cfg.two_phase != h0->cfg.two_phase ||
             h->cfg.curv_mode != h0->cfg.curv_mode || (h->cfg.n_modes > 0) != (h0->cfg.n_modes > 0) ||
-            h->P.phi_fix != h0->P.phi_fix)
-            return bad(LBM_EINVAL, "members differ in storage, phi storage, two_phase, curv_mode or forcing");
+            h->P.phi_fix != h0->P.phi_fix || (h->cfg.two_phase && h->cfg.ac_rk3) != (h0->cfg.two_phase && h0->cfg.ac_rk3))
+            return bad(LBM_EINVAL,
+                       "members differ in storage, phi storage or integrator, two_phase, curv_mode or forcing");
         if (h->stream != h0->stream) return bad(LBM_EINVAL, "members are on different streams");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch();
@@ -670,9 +706,11 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
     b->frc = h0->cfg.n_modes > 0;
     b->ml = h0->cfg.curv_mode == LBM_CURV_MLP;
     b->fix = h0->P.phi_fix != 0;
+    b->rk3 = h0->cfg.two_phase && h0->cfg.ac_rk3;
     for (lbm_handle *h : m) b->P.push_back(h->P);
     b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, b->tile);
-    if (b->grid <= 0) {
+    b->grid_ac = b->rk3 ? lbm::ac_stage_grid(b->tile) : 1;
+    if (b->grid <= 0 || b->grid_ac <= 0) {
         delete b;
         return bad(LBM_EHIP, "occupancy query failed");
     }
@@ -746,7 +784,7 @@ int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *tile_out, int *zc
     for (lbm_handle *h : b->m)
         shapes.push_back(std::to_string(h->cfg.nx) + "x" + std::to_string(h->cfg.ny) + "x" + std::to_string(h->cfg.nz));
     std::sort(shapes.begin(), shapes.end());
-    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d") + (b->fix ? "q" : "");
+    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d") + (b->fix ? "q" : "") + (b->rk3 ? "r" : "");
     for (const std::string &sh : shapes) key += "," + sh;
     auto apply = [&](int tile, int zc) -> int { return lbm_batch_set_tiling(b, tile, zc); };
     int best_tile = -1, best_zc = -1;
@@ -803,11 +841,13 @@ int lbm_batch_set_tiling(lbm_batch *b, int tile, int zchunk)
     if (tile != 64 && tile != 32) return b->fail(LBM_EINVAL, "tile must be 64 or 32");
     if (zchunk < 1) return b->fail(LBM_EINVAL, "zchunk must be >= 1");
     const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, tile);
-    if (grid <= 0) return b->fail(LBM_EHIP, "occupancy query failed");
+    const int grid_ac = b->rk3 ? lbm::ac_stage_grid(tile) : 1;
+    if (grid <= 0 || grid_ac <= 0) return b->fail(LBM_EHIP, "occupancy query failed");
     for (lbm::Params &P : b->P) set_tiling(P, tile, zchunk);
     b->tile = tile;
     b->zchunk = zchunk;
     b->grid = grid;
+    b->grid_ac = grid_ac;
     b->dirty = true;
     return LBM_OK;
 }

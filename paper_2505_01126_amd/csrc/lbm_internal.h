@@ -68,6 +68,7 @@ struct Buffers {
     void *phout;
     const float *uin;
     float *uout;
+    const void *phin0;  // phi^n for the Runge-Kutta stages of the phase field
 };
 
 hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,
@@ -79,6 +80,11 @@ int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, int tile);
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
                              uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, bool fix,
                              int tile, int grid, hipStream_t s);
+// one Runge-Kutta stage of the phase field: phout = rk_a phin0 + rk_b (phin + L(phin))
+int ac_stage_grid(int tile);
+hipError_t launch_ac_stage_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
+                                 uint32_t *counter, int parity, double rk_a, double rk_b, int tile, int grid,
+                                 hipStream_t s);
 hipError_t launch_moments(const Params &p, int storage, const void *fin, const void *phi, float *rho, float *pr,
                           float *u, double *phi_out, hipStream_t s);
 constexpr int HARVEST_BLOCKS = 1024;

@@ -557,9 +557,16 @@ __device__ __forceinline__ void lds_barrier()
 // One work item: the xy tile and z chunk with linear index L (x tile fastest,
 // then y tile, then z chunk) of one box.  Every thread of the workgroup calls
 // it; it leaves no LDS state that the next call relies on.
-template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0), bool FX = false>
-__device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L)
+//
+// ACO (Allen-Cahn only): one Runge-Kutta stage of the phase field and nothing
+// else: phi_out = rk_a phi^n + rk_b (phi_in + L(phi_in)) with phi_in staged in
+// the LDS ring (B.phin), phi^n read at the site (B.phin0), FP64 phi.
+template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0), bool FX = false,
+          bool ACO = false>
+__device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L, double rk_a = 0.0,
+                                          double rk_b = 1.0)
 {
+    static_assert(!ACO || (TP && !FX && !ML), "a Runge-Kutta stage needs the FP64 phase field");
     using T = typename Pop<S>::T;
     using PS = PhiStore<FX>;
     using PT = typename PS::T;
@@ -770,7 +777,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
         jz_left = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], um, uz_c);
     }
-    if (active) fetch_pops(z0);
+    if (!ACO && active) fetch_pops(z0);
 
     for (int z = z0; z < zend; z++) {
         const bool more = z + 1 < zend;
@@ -790,13 +797,13 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         float kfd = 0.f, gn = 0.f;
         bool sel = false;
         if (active) {
-            {
+            if constexpr (!ACO) {
                 float hf[27];
 #pragma unroll
                 for (int i = 0; i < 27; i++) hf[i] = Pop<S>::dec(hv[i]);
                 moments10(hf, M);
             }
-            if (!kLatePrefetch && more) fetch_pops(z + 1);
+            if (!ACO && !kLatePrefetch && more) fetch_pops(z + 1);
 
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
@@ -824,7 +831,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                         const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
                         ph[i] = pl[lc + CY(i) * PX + CX(i)];
                     }
-                    phi_stencil(ph, G);
+                    if constexpr (!ACO) phi_stencil(ph, G);
                     if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
                     const float4 *q0 = sq[(z - 1 + 3) % 3];
                     const float4 *q1 = sq[(z + 3) % 3];
@@ -847,11 +854,16 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
                 }
-                phout[(size_t)own] = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
+                if constexpr (ACO)
+                    phout[(size_t)own] = rk_a * gconst((const double *)B.phin0)[own] +
+                                         rk_b * (po + ((acc[0] + acc[1]) + (acc[2] + acc[3])));
+                else
+                    phout[(size_t)own] = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
                 if (more) po = phin[(size_t)own + plane];
             }
-            if (kLatePrefetch && more) fetch_pops(z + 1);
+            if (!ACO && kLatePrefetch && more) fetch_pops(z + 1);
         }
+        if constexpr (ACO) continue;
         // surface tension: finite differences, or blended with the network
         // evaluated on the wave's selected interface cells (all lanes together)
         float fs[3] = {0.f, 0.f, 0.f};
@@ -900,6 +912,35 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 // first[b] <= k < first[b + 1].  The queue counter of this launch is
 // counter[parity]; the launch clears the other one for the next launch on the
 // stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
+// One Runge-Kutta stage of the phase field of one or many boxes, the same
+// persistent queue over the same work items (buf[b].phin: the stage input,
+// buf[b].phin0: phi^n, buf[b].phout: the stage output).
+template <int TW>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_ac_stage_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+                 int nbox, uint32_t *counter, int parity, double rk_a, double rk_b)
+{
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.y * TW + threadIdx.x;
+    const uint32_t total = first[nbox];
+    if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[parity], 1u);
+        __syncthreads();
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        step_tile<0, true, false, false, TW, true, false, true>(tab[b], buf[b], item - first[b], rk_a, rk_b);
+    }
+}
+
 template <int S, bool TP, bool FRC, bool ML, int TW, bool FX>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(ML ? 1 : 3)))
 k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
@@ -1226,6 +1267,30 @@ hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32
     }
     LBM_DISPATCH(storage, tp, frc, ml, LBM_STEP_CALL);
 #undef STEP_CALL
+    return hipGetLastError();
+}
+
+int ac_stage_grid(int tile)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (tile == 32)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ac_stage_batch<32>, NTHREADS, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ac_stage_batch<64>, NTHREADS, 0);
+    return per_cu * cus;
+}
+
+hipError_t launch_ac_stage_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
+                                 uint32_t *counter, int parity, double rk_a, double rk_b, int tile, int grid,
+                                 hipStream_t s)
+{
+    dim3 g(grid), block(tile, NTHREADS / tile, 1);
+    if (tile == 32)
+        hipLaunchKernelGGL(k_ac_stage_batch<32>, g, block, 0, s, tab, buf, first, nbox, counter, parity, rk_a, rk_b);
+    else
+        hipLaunchKernelGGL(k_ac_stage_batch<64>, g, block, 0, s, tab, buf, first, nbox, counter, parity, rk_a, rk_b);
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ class lbm_config(C.Structure):
         ("mlp_k_lo", C.c_double), ("mlp_k_hi", C.c_double),
         ("phi_storage", C.c_int32), ("reserved", C.c_int32),
         ("gravity", C.c_double * 3), ("tau_g", C.c_double),
+        ("ac_rk3", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -104,7 +105,7 @@ def _check(rc, handle=None, what=""):
 
 def make_config(shape, tau, two_phase=False, storage="f32", rho_l=1.0, rho_g=1.0, sigma=0.0, mobility=0.0,
                 width=4.0, p0=1.0, modes=None, zchunk=0, curv_mode="fd", mlp_k_lo=0.0, mlp_k_hi=0.0,
-                phi_storage="f64", gravity=(0.0, 0.0, 0.0), tau_g=0.0):
+                phi_storage="f64", gravity=(0.0, 0.0, 0.0), tau_g=0.0, ac_rk3=False):
     """Build an lbm_config; returns (config, keepalive) where keepalive owns the mode table."""
     nz, ny, nx = shape
     tab = None if modes is None or len(modes) == 0 else np.ascontiguousarray(modes, dtype=np.float64)
@@ -113,7 +114,7 @@ def make_config(shape, tau, two_phase=False, storage="f32", rho_l=1.0, rho_g=1.0
                      0 if tab is None else len(tab), int(zchunk),
                      None if tab is None else tab.ctypes.data_as(C.POINTER(C.c_double)),
                      float(mlp_k_lo), float(mlp_k_hi), PHI_STORAGE.get(phi_storage, phi_storage), 0,
-                     (C.c_double * 3)(*[float(v) for v in gravity]), float(tau_g))
+                     (C.c_double * 3)(*[float(v) for v in gravity]), float(tau_g), int(ac_rk3), 0)
     return cfg, tab
 
 
@@ -251,7 +252,7 @@ class Lattice:
     def __init__(self, shape, tau, phi0=None, u0=None, pstar0=None, two_phase=None, storage="f32", rho_l=1.0,
                  rho_g=1.0, sigma=0.0, mobility=0.0, width=4.0, p0=1.0, modes=None, zchunk=0, curv_mode="fd",
                  mlp_k_lo=0.0, mlp_k_hi=0.0, phi_storage="f64", gravity=(0.0, 0.0, 0.0), tau_g=0.0,
-                 device="cuda:0"):
+                 ac_rk3=False, device="cuda:0"):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -263,7 +264,7 @@ class Lattice:
         self.two_phase = bool(two_phase)
         self.cfg, self._tab = make_config(self.shape, tau, self.two_phase, storage, rho_l, rho_g, sigma, mobility,
                                           width, p0, modes, zchunk, curv_mode, mlp_k_lo, mlp_k_hi, phi_storage,
-                                          gravity, tau_g)
+                                          gravity, tau_g, ac_rk3)
         nbytes = lbm_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise LbmError("invalid configuration")

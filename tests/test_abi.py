@@ -32,7 +32,7 @@ def test_abi_version_and_constants():
     assert lbm.lbm_abi_version() == ver
     assert int(re.search(r"#define LBM_NRED (\d+)", text).group(1)) == lbm.NRED
     assert int(re.search(r"#define LBM_MLP_NPARAM (\d+)", text).group(1)) == lbm.MLP_NPARAM
-    assert C.sizeof(lbm.lbm_config) == 152
+    assert C.sizeof(lbm.lbm_config) == 160
 
 
 def test_config_struct_matches_header(tmp_path):
@@ -74,7 +74,8 @@ def test_workspace_bytes_counts_state():
                                 dict(tau=0.8, storage="f16", modes=[[3, 0, 0] + [0] * 6]),
                                 dict(tau=0.8, two_phase=True, phi_storage=2),
                                 dict(tau=0.8, two_phase=True, tau_g=0.45),
-                                dict(tau=0.8, two_phase=True, gravity=(0.0, float("nan"), 0.0))])
+                                dict(tau=0.8, two_phase=True, gravity=(0.0, float("nan"), 0.0)),
+                                dict(tau=0.8, two_phase=True, ac_rk3=1, phi_storage="fix32")])
 def test_invalid_configs_rejected_on_host(kw):
     shape = kw.pop("shape", (16, 16, 16))
     tau = kw.pop("tau")
