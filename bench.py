@@ -66,7 +66,9 @@ def parse_variant(key):
 
 def bytes_per_lup(st, phs="f64", rk3=False):
     return BYTES_PER_LUP[st] - PHI_BYTES_SAVED[phs] + (2 * RK3_STAGE_BYTES if rk3 else 0)
-KERNEL_SOURCES = ["paper_2505_01126_amd/csrc/lbm_kernels.hip", "paper_2505_01126_amd/csrc/lbm_internal.h"]
+KERNEL_SOURCES = ["paper_2505_01126_amd/csrc/lbm_step.h", "paper_2505_01126_amd/csrc/lbm_step_s0.hip",
+                  "paper_2505_01126_amd/csrc/lbm_step_s1.hip", "paper_2505_01126_amd/csrc/lbm_step_s2.hip",
+                  "paper_2505_01126_amd/csrc/lbm_kernels.hip", "paper_2505_01126_amd/csrc/lbm_internal.h"]
 
 
 def kernel_sha():

@@ -213,7 +213,8 @@ int lbm_harvest(lbm_handle *h, const double *centers, const double *radii, int n
  * bit-identical fields to the same box advanced alone with lbm_step.
  *
  * Members are lbm_handle's created with lbm_init; they must share storage,
- * phi_storage, two_phase, curv_mode and the presence of a body force, and be on the same
+ * phi_storage, ac_rk3, two_phase, curv_mode, the presence of a body force and
+ * whether buoyancy or a viscosity contrast is on, and be on the same
  * stream (the first member's).  They must outlive the batch.  A member may
  * still be stepped, read or reduced on its own; the batch picks up its state
  * at the next lbm_batch_step. */
@@ -227,7 +228,8 @@ size_t lbm_batch_bytes(int n);
  * device buffer of table_bytes >= lbm_batch_bytes(n), 256-byte aligned, owned
  * by the caller and used by the batch until lbm_batch_destroy.  Errors:
  * LBM_EINVAL (n, NULL or repeated member, mixed storage / phi storage /
- * two_phase / curv_mode / forcing / stream), LBM_ENOSPACE, LBM_EHIP. */
+ * integrator / two_phase / curv_mode / forcing / buoyancy or viscosity
+ * contrast / stream), LBM_ENOSPACE, LBM_EHIP. */
 int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d_table, size_t table_bytes);
 
 /* Advance every member by nsteps (>= 0), asynchronously on the members' stream.

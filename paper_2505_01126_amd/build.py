@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
 PROBE = os.path.join(PKG, "bw_probe")  # standalone bandwidth probe (not part of the library)
-SOURCES = ["lbm_kernels.hip", "lbm_mlp.hip", "lbm_api.hip"]
+SOURCES = ["lbm_step_s0.hip", "lbm_step_s1.hip", "lbm_step_s2.hip", "lbm_kernels.hip", "lbm_mlp.hip", "lbm_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

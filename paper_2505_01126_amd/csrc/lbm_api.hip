@@ -133,7 +133,7 @@ struct lbm_batch {
     char *table = nullptr;
     size_t off_tab = 0, off_buf = 0, off_first = 0, off_counter = 0;
     int storage = 0, grid = 0, parity = 0, zchunk = 32, tile = 64;
-    bool tp = false, frc = false, ml = false, fix = false, rk3 = false, dirty = true;
+    bool tp = false, frc = false, ml = false, fix = false, rk3 = false, phys = false, dirty = true;
     int grid_ac = 0;  // persistent grid of the Runge-Kutta stage kernel
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -630,7 +630,7 @@ hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
 {
     const int n = (int)b->m.size();
     hipError_t e = lbm::launch_step_batch(b->d_tab(), b->d_buf(0, parity), b->d_first(), n, b->d_counter(), parity,
-                                          b->storage, b->tp, b->frc, b->ml, b->fix, b->tile, b->grid, s);
+                                          b->storage, b->tp, b->frc, b->ml, b->fix, b->phys, b->tile, b->grid, s);
     if (e == hipSuccess && b->rk3)
         e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(1, parity), b->d_first(), n, b->d_counter() + 2, parity,
                                        0.75, 0.25, b->tile, b->grid_ac, s);
@@ -686,9 +686,10 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
         if (!h) return bad(LBM_EINVAL, "NULL member");
         if (h->cfg.storage != h0->cfg.storage || h->cfg.two_phase != h0->cfg.two_phase ||
             h->cfg.curv_mode != h0->cfg.curv_mode || (h->cfg.n_modes > 0) != (h0->cfg.n_modes > 0) ||
-            h->P.phi_fix != h0->P.phi_fix || (h->cfg.two_phase && h->cfg.ac_rk3) != (h0->cfg.two_phase && h0->cfg.ac_rk3))
-            return bad(LBM_EINVAL,
-                       "members differ in storage, phi storage or integrator, two_phase, curv_mode or forcing");
+            h->P.phi_fix != h0->P.phi_fix || (h->cfg.two_phase && h->cfg.ac_rk3) != (h0->cfg.two_phase && h0->cfg.ac_rk3) ||
+            (h->P.gravity_on || h->P.tau_g > 0.0f) != (h0->P.gravity_on || h0->P.tau_g > 0.0f))
+            return bad(LBM_EINVAL, "members differ in storage, phi storage or integrator, two_phase, curv_mode, "
+                                   "forcing, or in having buoyancy or a viscosity contrast");
         if (h->stream != h0->stream) return bad(LBM_EINVAL, "members are on different streams");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch();
@@ -707,8 +708,9 @@ int lbm_batch_create(lbm_batch **out, lbm_handle *const *members, int n, void *d
     b->ml = h0->cfg.curv_mode == LBM_CURV_MLP;
     b->fix = h0->P.phi_fix != 0;
     b->rk3 = h0->cfg.two_phase && h0->cfg.ac_rk3;
+    b->phys = h0->P.gravity_on || h0->P.tau_g > 0.0f;
     for (lbm_handle *h : m) b->P.push_back(h->P);
-    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, b->tile);
+    b->grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, b->phys, b->tile);
     b->grid_ac = b->rk3 ? lbm::ac_stage_grid(b->tile) : 1;
     if (b->grid <= 0 || b->grid_ac <= 0) {
         delete b;
@@ -784,7 +786,7 @@ int lbm_batch_tune(lbm_batch *b, int steps_per_candidate, int *tile_out, int *zc
     for (lbm_handle *h : b->m)
         shapes.push_back(std::to_string(h->cfg.nx) + "x" + std::to_string(h->cfg.ny) + "x" + std::to_string(h->cfg.nz));
     std::sort(shapes.begin(), shapes.end());
-    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d") + (b->fix ? "q" : "") + (b->rk3 ? "r" : "");
+    std::string key = std::to_string(b->storage) + (b->tp ? "t" : "s") + (b->frc ? "f" : "-") + (b->ml ? "m" : "d") + (b->fix ? "q" : "") + (b->rk3 ? "r" : "") + (b->phys ? "g" : "");
     for (const std::string &sh : shapes) key += "," + sh;
     auto apply = [&](int tile, int zc) -> int { return lbm_batch_set_tiling(b, tile, zc); };
     int best_tile = -1, best_zc = -1;
@@ -840,7 +842,7 @@ int lbm_batch_set_tiling(lbm_batch *b, int tile, int zchunk)
     if (!b) return LBM_EINVAL;
     if (tile != 64 && tile != 32) return b->fail(LBM_EINVAL, "tile must be 64 or 32");
     if (zchunk < 1) return b->fail(LBM_EINVAL, "zchunk must be >= 1");
-    const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, tile);
+    const int grid = lbm::batch_grid(b->storage, b->tp, b->frc, b->ml, b->fix, b->phys, tile);
     const int grid_ac = b->rk3 ? lbm::ac_stage_grid(tile) : 1;
     if (grid <= 0 || grid_ac <= 0) return b->fail(LBM_EHIP, "occupancy query failed");
     for (lbm::Params &P : b->P) set_tiling(P, tile, zchunk);

@@ -76,10 +76,11 @@ hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, 
 // the time step of one or many boxes in one persistent launch (see k_step_batch)
 // tile: workgroup tile width in x, 64 (64 x 4 sites) or 32 (32 x 8)
 // fix: phi held as int32 fixed point (two-phase only)
-int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, int tile);
+// phys: buoyancy / phase-dependent relaxation time compiled in (two-phase only)
+int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, bool phys, int tile);
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
                              uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, bool fix,
-                             int tile, int grid, hipStream_t s);
+                             bool phys, int tile, int grid, hipStream_t s);
 // one Runge-Kutta stage of the phase field: phout = rk_a phin0 + rk_b (phin + L(phin))
 int ac_stage_grid(int tile);
 hipError_t launch_ac_stage_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
