@@ -1,0 +1,116 @@
+"""Options of the step used together, against the FP64 oracle.
+
+* the learned curvature with buoyancy, a viscosity contrast and the
+  Runge-Kutta phase field (FP32 populations);
+* the int32 fixed-point phase field with buoyancy (the box-mean density comes
+  from the exact integer sum of phi; sum phi stays bit-exact);
+* a batch of boxes with buoyancy and a viscosity contrast, bit-identical to
+  the boxes stepped alone, and a batch that mixes them with plain boxes is
+  rejected.
+Bars as for the single options: u relative L2 below 1e-5 (FP32 populations;
+1e-3 where the learned curvature's fp16 rounding of activations can flip),
+phi within 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_01126_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TWO_PHASE = dict(rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+
+
+def _weights(seed):
+    w = np.random.default_rng(seed).standard_normal(6212) * 0.25
+    w[6208 + 1:6212] = [0.6, 0.5, 0.4]  # normal outputs near unit length: the blend branch runs
+    return w.astype(np.float16).astype(np.float64)
+
+
+def test_learned_curvature_buoyancy_viscosity_runge_kutta():
+    import torch
+
+    from paper_2505_01126_amd import lbm
+
+    shape = (24, 20, 70)
+    phi_a, _ = I.droplet(shape, 3.0, 4.0, center=(20.3, 10.1, 12.2), inside=0.0)
+    phi_b, _ = I.droplet(shape, 4.0, 4.0, center=(52.7, 9.6, 11.4), inside=0.0)
+    phi0 = np.minimum(phi_a, phi_b)
+    u0 = I.random_u(shape, 0.005, seed=41)
+    w = _weights(42)
+    kw = dict(phi0=phi0, u0=u0, gravity=(0.0, 1e-6, -5e-6), tau_g=0.65, **TWO_PHASE)
+    print(f"case mlp+gravity+tau_g+rk3 shape={shape}", flush=True)
+    g = lbm.Lattice(shape, 0.8, zchunk=8, curv_mode="mlp", ac_rk3=True, **kw)
+    g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
+    r0 = g.reduce()
+    g.step(40)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    r1 = g.reduce()
+    g.close()
+    o = O.Oracle(shape, 0.8, curv_mode=1, mlp=w, ac_rk3=True, **kw)
+    o.step(40)
+    mo = o.moments()
+    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    dphi = np.abs(m["phi"] - mo["phi"]).max()
+    print(f"mlp + buoyancy + tau_g + rk3: u rel err {e:.3e}, phi max abs {dphi:.3e}")
+    assert e < 1e-3
+    assert dphi < 1e-5
+    assert abs(r1[0] - r0[0]) / r0[0] < 1e-12
+
+
+def test_fixed_point_phi_with_buoyancy():
+    from paper_2505_01126_amd import lbm
+
+    shape = (26, 20, 70)
+    phi0, _, _ = I.bubble_pack(shape, 2, 8.0, seed=43)
+    u0 = I.random_u(shape, 0.005, seed=44)
+    kw = dict(phi0=phi0, u0=u0, gravity=(0.0, 0.0, -1e-5), tau_g=0.6, **TWO_PHASE)
+    print(f"case fix32+gravity shape={shape}", flush=True)
+    g = lbm.Lattice(shape, 0.8, zchunk=8, phi_storage="fix32", **kw)
+    q = np.rint(phi0 * 2.0 ** 30).astype(np.int64)
+    expect = float(q.sum()) * 2.0 ** -30
+    g.step(100)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    r = g.reduce()
+    g.close()
+    o = O.Oracle(shape, 0.8, **kw)
+    o.step(100)
+    mo = o.moments()
+    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    dphi = np.abs(m["phi"] - mo["phi"]).max()
+    print(f"fix32 + buoyancy: u rel err {e:.3e}, phi max abs {dphi:.3e}, sum phi {r[0]!r} vs {expect!r}")
+    assert e < 1e-5
+    assert dphi < 1e-5
+    assert r[0] == expect
+
+
+def test_batch_with_buoyancy_bit_identical_and_rejects_mixed():
+    from paper_2505_01126_amd import lbm
+
+    shapes = [(16, 20, 70), (32, 32, 32), (20, 36, 20)]
+    boxes = []
+    for k, shape in enumerate(shapes):
+        phi0, _ = I.droplet(shape, 4.0, 4.0, inside=0.0)
+        boxes.append((shape, phi0, I.random_u(shape, 0.01, seed=50 + k)))
+
+    def make(phys=True):
+        extra = dict(gravity=(0.0, 0.0, -1e-5), tau_g=0.6) if phys else {}
+        return [lbm.Lattice(s, 0.7, phi0=p, u0=u, storage="f16", **TWO_PHASE, **extra) for s, p, u in boxes]
+
+    alone = make()
+    for g in alone:
+        g.step(5)
+    members = make()
+    b = lbm.Batch(members)
+    b.step(2)
+    b.set_tiling(32, 16)
+    b.step(3)
+    for i, g in enumerate(members):
+        a, c = alone[i].moments(), g.moments()
+        for k in a:
+            assert bool((a[k] == c[k]).all()), f"box {i}: field {k} differs"
+    b.close()
+    plain = make(phys=False)[0]
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch([alone[0], plain])
