@@ -80,7 +80,7 @@ typedef struct {
     double width;        /* interface width delta; kappa = 4 D / delta */
     double p0;           /* pressure gauge P0: storage shift and the p* used when no initial p* is given */
     int32_t n_modes;     /* forcing rows, 0 .. LBM_MAX_MODES */
-    int32_t zchunk;      /* z planes per workgroup (0 = library default) */
+    int32_t zchunk;      /* z planes per work item (0 = library default: 32 for FP32 storage, 64 for FP16/BF16) */
     const double *modes; /* HOST table [n_modes][9]: kx ky kz Re(Ax) Im(Ax) Re(Ay) Im(Ay) Re(Az) Im(Az);
                             integer wave numbers with |kx| <= 2; body acceleration
                             a(x) = sum_m Re(A_m exp(2 pi i (kx x/nx + ky y/ny + kz z/nz)));

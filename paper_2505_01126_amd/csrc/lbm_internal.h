@@ -69,6 +69,8 @@ struct Buffers {
     const float *uin;
     float *uout;
     const void *phin0;  // phi^n for the Runge-Kutta stages of the phase field
+    void *mlpy;         // learned curvature: network outputs (float4 per site)
+    void *mlpf;         // and selection flags (one byte per site), from the pass before the step
 };
 
 hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,
@@ -81,6 +83,10 @@ int batch_grid(int storage, bool tp, bool frc, bool ml, bool fix, bool phys, int
 hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
                              uint32_t *counter, int parity, int storage, bool tp, bool frc, bool ml, bool fix,
                              bool phys, int tile, int grid, hipStream_t s);
+// the learned-curvature pass ahead of the step (fix: fixed-point phi)
+int mlp_pass_grid(bool fix, int tile);
+hipError_t launch_mlp_pass_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
+                                 uint32_t *counter, int parity, bool fix, int tile, int grid, hipStream_t s);
 // one Runge-Kutta stage of the phase field: phout = rk_a phin0 + rk_b (phin + L(phin))
 int ac_stage_grid(int tile);
 hipError_t launch_ac_stage_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,

@@ -275,6 +275,37 @@ hipError_t launch_step_batch(const Params *tab, const Buffers *buf, const uint32
     return step_launch<2>(tab, buf, first, nbox, counter, parity, tp, frc, ml, fix, phys, tile, grid, s);
 }
 
+int mlp_pass_grid(bool fix, int tile)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (tile == 32) {
+        if (fix) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_pass_batch<32, true>, NTHREADS, 0);
+        else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_pass_batch<32, false>, NTHREADS, 0);
+    } else {
+        if (fix) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_pass_batch<64, true>, NTHREADS, 0);
+        else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_pass_batch<64, false>, NTHREADS, 0);
+    }
+    return per_cu * cus;
+}
+
+hipError_t launch_mlp_pass_batch(const Params *tab, const Buffers *buf, const uint32_t *first, int nbox,
+                                 uint32_t *counter, int parity, bool fix, int tile, int grid, hipStream_t s)
+{
+    dim3 g(grid), block(tile, NTHREADS / tile, 1);
+#define PASS(TW_, X_) hipLaunchKernelGGL((k_mlp_pass_batch<TW_, X_>), g, block, 0, s, tab, buf, first, nbox, counter, parity)
+    if (tile == 32) {
+        if (fix) PASS(32, true);
+        else PASS(32, false);
+    } else {
+        if (fix) PASS(64, true);
+        else PASS(64, false);
+    }
+#undef PASS
+    return hipGetLastError();
+}
+
 int ac_stage_grid(int tile)
 {
     int dev = 0, cus = 0, per_cu = 0;

@@ -99,8 +99,9 @@ __device__ __forceinline__ half8 ld8(const _Float16 *p)
 
 // Forward pass of one 16-sample tile held by a wave.  xa: this lane's A
 // fragment of the inputs (row l%16, k = 8(l/16)..+7).  h1, h2: wave-private
-// LDS tiles [16][64] receiving the fp16 activations; returns the FP32 outputs
-// in C layout (column o = l%16 < 4, rows 4(l/16)+i).
+// LDS tiles [16][64] receiving the fp16 activations (they may be one tile: the
+// MFMAs consume every lane's reads of h1 before the first write of h2);
+// returns the FP32 outputs in C layout (column o = l%16 < 4, rows 4(l/16)+i).
 __device__ __forceinline__ f32x4 forward_tile(const MlpW &L, half8 xa, _Float16 (*h1)[NH], _Float16 (*h2)[NH],
                                               int lane)
 {
@@ -135,12 +136,14 @@ __device__ __forceinline__ f32x4 forward_tile(const MlpW &L, half8 xa, _Float16 
     return y;
 }
 
-// Wave-private LDS scratch for the in-step network evaluation.
+// Wave-private LDS scratch for the network evaluation of selected cells: the
+// staged inputs [16][KIN] and the activations of both hidden layers share one
+// tile (each is read into registers, and consumed by the MFMAs, before the
+// next is written).
 struct MlpWave {
-    _Float16 stage[16][KIN];
-    _Float16 h1[16][NH];
-    _Float16 h2[16][NH];
+    _Float16 h[16][NH];
     float y[16][NOUT];
+    __device__ _Float16 (*stage())[KIN] { return (_Float16 (*)[KIN]) & h[0][0]; }
 };
 
 // Network outputs for the lanes of this wave with sel set (every lane of the
@@ -149,6 +152,7 @@ struct MlpWave {
 __device__ __forceinline__ void mlp_wave(const MlpW &W, MlpWave &S, bool sel, const float (&ph)[27], float (&y)[4],
                                          int lane)
 {
+    _Float16 (*stage)[KIN] = S.stage();
     const unsigned long long bal = __ballot(sel);
     const int nsel = __popcll(bal);
     const int rank = __popcll(bal & ((1ull << lane) - 1ull));
@@ -157,19 +161,19 @@ __device__ __forceinline__ void mlp_wave(const MlpW &W, MlpWave &S, bool sel, co
         const bool mine = sel && rank >= t && rank < t + 16;
         if (mine) {
 #pragma unroll
-            for (int i = 0; i < NIN; i++) S.stage[rank - t][i] = (_Float16)(2.0f * ph[i] - 1.0f);
+            for (int i = 0; i < NIN; i++) stage[rank - t][i] = (_Float16)(2.0f * ph[i] - 1.0f);
 #pragma unroll
-            for (int i = NIN; i < KIN; i++) S.stage[rank - t][i] = (_Float16)0.0f;
+            for (int i = NIN; i < KIN; i++) stage[rank - t][i] = (_Float16)0.0f;
         }
         wave_lds_sync();
         half8 xa;
         if (t + row < nsel) {
-            xa = ld8(&S.stage[row][8 * kq]);
+            xa = ld8(&stage[row][8 * kq]);
         } else {
 #pragma unroll
             for (int j = 0; j < 8; j++) xa[j] = (_Float16)0.0f;
         }
-        const f32x4 o = forward_tile(W, xa, S.h1, S.h2, lane);
+        const f32x4 o = forward_tile(W, xa, S.h, S.h, lane);
         if (row < NOUT)
 #pragma unroll
             for (int i = 0; i < 4; i++) S.y[4 * kq + i][row] = o[i];

@@ -567,11 +567,20 @@ __device__ __forceinline__ void lds_barrier()
 // else: phi_out = rk_a phi^n + rk_b (phi_in + L(phi_in)) with phi_in staged in
 // the LDS ring (B.phin), phi^n read at the site (B.phin0), FP64 phi.
 template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0), bool FX = false,
-          bool ACO = false, bool PH = false>
+          bool ACO = false, bool PH = false, bool PRE = false>
 __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L, double rk_a = 0.0,
                                           double rk_b = 1.0)
 {
     static_assert(!ACO || (TP && !FX && !ML), "a Runge-Kutta stage needs the FP64 phase field");
+    static_assert(!PRE || (TP && ML && !ACO), "the network pass belongs to the learned curvature");
+    // PRE: the learned-curvature pass that runs before the step: for every
+    // interface cell that the curvature criterion selects, the network output
+    // goes to B.mlpy (float4 per site) and a flag to B.mlpf (one byte per site,
+    // 0 or 1 for every site); nothing else.  The step with ML set then reads
+    // the flag and, where it is set, the output, so the network's registers and
+    // LDS are not part of the step kernel.
+    constexpr bool NET = ML && PRE;  // the network is evaluated in this kernel
+    constexpr bool LBM = !ACO && !PRE;  // the populations are streamed and collided
     using T = typename Pop<S>::T;
     using PS = PhiStore<FX>;
     using PT = typename PS::T;
@@ -627,7 +636,12 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // pull-stream of plane z into hv: h_i(x) = h^post_i(x - c_i)
     // raw storage values: decoded only where they are consumed, so the loads of
     // the next plane stay in flight (a decode right after the load would wait for it)
-    T hv[27];
+    // 16-bit values are held zero-extended in full registers: packed two to a
+    // register, each pair would wait for its loads on arrival (a 16-bit load
+    // into half a register depends on the other half), which would make the
+    // prefetch synchronous
+    using HT = std::conditional_t<sizeof(T) == 2, uint32_t, T>;
+    HT hv[27];
     const size_t pstride = (size_t)27 * plane;  // elements per z plane of populations
     const uint32_t pbytes = 27u * plane * ES;   // bytes per z plane of populations
     auto fetch_pops = [&](int z) {
@@ -639,7 +653,11 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         uint32_t soff = 0;
 #pragma unroll
         for (int i = 0; i < 27; i++) {
-            hv[i] = bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, soff);
+            if constexpr (std::is_same_v<HT, T>)
+                hv[i] = bload<T>(zsrc[CZ(i) + 1], src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, soff);
+            else
+                hv[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(zsrc[CZ(i) + 1],
+                                                                       src_xy[(CY(i) + 1) * 3 + CX(i) + 1] * ES, soff, 0);
             soff += plane * ES;
             asm volatile("" : "+s"(soff));
         }
@@ -648,15 +666,16 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
     // the global xy offset of every position of the phi tile
     __shared__ float sphi[TP ? NRING : 1][TP ? PLANE : 1];
-    __shared__ float4 sq[TP ? 3 : 1][TP ? QPLANE : 1];  // Q (x, y, z, unused) per point
-    __shared__ float sjx[TP ? NXF : 1];
-    __shared__ float sjy[TP ? NYF : 1];
+    constexpr bool AC = TP && !PRE;  // the Allen-Cahn update runs here
+    __shared__ float4 sq[AC ? 3 : 1][AC ? QPLANE : 1];  // Q (x, y, z, unused) per point
+    __shared__ float sjx[AC ? NXF : 1];
+    __shared__ float sjy[AC ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
     // learned curvature: weights and per-wave scratch
-    __shared__ char mlp_raw[ML ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
+    __shared__ char mlp_raw[NET ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
     MlpW &smw = *(MlpW *)mlp_raw;
-    MlpWave *smwave = (MlpWave *)(mlp_raw + (ML ? sizeof(MlpW) : 0));
-    if constexpr (ML) load_weights(gconst((const uint16_t *)P.mlp), smw, tid, NTHREADS);
+    MlpWave *smwave = (MlpWave *)(mlp_raw + (NET ? sizeof(MlpW) : 0));
+    if constexpr (NET) load_weights(gconst((const uint16_t *)P.mlp), smw, tid, NTHREADS);
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
     bool f_isx[FROUNDS];
@@ -664,6 +683,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     float f_ul[FROUNDS], f_ur[FROUNDS];  // prefetched face velocities
     float jz_left = 0.f, uz_c = 0.f, uz_n = 0.f;
     PT po = 0;              // prefetched own phi
+    uint32_t mflag = 0;     // learned curvature: prefetched selection flag of the own site
 
     auto fetch_plane = [&](int z) {
         const LBM_GLOBAL PT *src = phin + (size_t)modi(z, nz) * plane;
@@ -769,20 +789,23 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         }
         fetch_plane(z0 + 3);
         lds_barrier();
-        fetch_face_u(z0);
-        compute_q(z0 - 1);
-        compute_q(z0);
-        // z face below the first plane: cells z0-3 .. z0+2, velocities at z0-1, z0
-        const float um = uz_in[(uint32_t)modi(z0 - 1, nz) * plane + own_xy];
-        uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
-        uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
-        po = phin[(size_t)z0 * plane + own_xy];
-        float v[6];
+        if constexpr (!PRE) {
+            fetch_face_u(z0);
+            compute_q(z0 - 1);
+            compute_q(z0);
+            // z face below the first plane: cells z0-3 .. z0+2, velocities at z0-1, z0
+            const float um = uz_in[(uint32_t)modi(z0 - 1, nz) * plane + own_xy];
+            uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
+            uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
+            po = phin[(size_t)z0 * plane + own_xy];
+            if constexpr (ML) mflag = gconst((const uint8_t *)B.mlpf)[(size_t)z0 * plane + own_xy];
+            float v[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
-        jz_left = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], um, uz_c);
+            for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
+            jz_left = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], um, uz_c);
+        }
     }
-    if (!ACO && active) fetch_pops(z0);
+    if (LBM && active) fetch_pops(z0);
 
     for (int z = z0; z < zend; z++) {
         const bool more = z + 1 < zend;
@@ -790,9 +813,11 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             store_plane(z + 3);
             if (more) fetch_plane(z + 4);
             lds_barrier();
-            compute_q(z + 1);
-            compute_faces(z);
-            if (more) fetch_face_u(z + 1);
+            if constexpr (!PRE) {
+                compute_q(z + 1);
+                compute_faces(z);
+                if (more) fetch_face_u(z + 1);
+            }
             lds_barrier();
         }
         const uint32_t own = (uint32_t)z * plane + own_xy;
@@ -801,14 +826,50 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         float ph[27];
         float kfd = 0.f, gn = 0.f;
         bool sel = false;
+        if constexpr (PRE) {
+            // the learned-curvature pass: stencil and criterion, only in waves
+            // that hold an interface cell (most waves hold none)
+            const float *pm = sphi[ring(z - 1)];
+            const float *pc = sphi[ring(z)];
+            const float *pp = sphi[ring(z + 1)];
+            const float c0 = pc[lc];
+            const bool cand = active && c0 > 0.02f && c0 < 0.98f;
+            float y[4] = {0.f, 0.f, 0.f, 0.f};
+            if (__ballot(cand) != 0ull) {
+                if (cand) {
+#pragma unroll
+                    for (int i = 0; i < 27; i++) {
+                        const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
+                        ph[i] = pl[lc + CY(i) * PX + CX(i)];
+                    }
+                    phi_stencil(ph, G);
+                    sel = mlp_select(G, P, kfd, gn);
+                }
+                mlp_wave(smw, smwave[tid >> 6], sel, ph, y, tid & 63);
+            }
+            if (active) {
+                gmut((uint8_t *)B.mlpf)[own] = sel ? 1 : 0;
+                if (sel) {
+                    LBM_GLOBAL float *yo = gmut((float *)B.mlpy) + 4 * (size_t)own;
+                    yo[0] = y[0];
+                    yo[1] = y[1];
+                    yo[2] = y[2];
+                    yo[3] = y[3];
+                }
+            }
+            continue;
+        }
         if (active) {
-            if constexpr (!ACO) {
+            if constexpr (LBM) {
                 float hf[27];
 #pragma unroll
-                for (int i = 0; i < 27; i++) hf[i] = Pop<S>::dec(hv[i]);
+                for (int i = 0; i < 27; i++) {
+                    if constexpr (std::is_same_v<HT, T>) hf[i] = Pop<S>::dec(hv[i]);
+                    else hf[i] = Pop<S>::dec(__builtin_bit_cast(T, (uint16_t)hv[i]));
+                }
                 moments10(hf, M);
             }
-            if (!ACO && !kLatePrefetch && more) fetch_pops(z + 1);
+            if (LBM && !kLatePrefetch && more) fetch_pops(z + 1);
 
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
@@ -866,18 +927,23 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     phout[(size_t)own] = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
                 if (more) po = phin[(size_t)own + plane];
             }
-            if (!ACO && kLatePrefetch && more) fetch_pops(z + 1);
+            if (LBM && kLatePrefetch && more) fetch_pops(z + 1);
         }
         if constexpr (ACO) continue;
         // surface tension: finite differences, or blended with the network
-        // evaluated on the wave's selected interface cells (all lanes together)
+        // output that the learned-curvature pass left for the selected cells
         float fs[3] = {0.f, 0.f, 0.f};
         if constexpr (ML) {
-            float y[4] = {0.f, 0.f, 0.f, 0.f};
-            mlp_wave(smw, smwave[tid >> 6], sel, ph, y, tid & 63);
             if (active) {
-                if (sel) surface_blend(G, P, kfd, gn, y, fs);
-                else surface_fd(G, P, fs);
+                const uint32_t use = mflag;
+                if (more) mflag = gconst((const uint8_t *)B.mlpf)[(size_t)own + plane];  // next plane's
+                if (use) {
+                    const LBM_GLOBAL float *yi = gconst((const float *)B.mlpy) + 4 * (size_t)own;
+                    const float y[4] = {yi[0], yi[1], yi[2], yi[3]};
+                    surface_blend(G, P, kfd, gn, y, fs);
+                } else {
+                    surface_fd(G, P, fs);
+                }
             }
         } else if constexpr (TP) {
             if (active) surface_fd(G, P, fs);
@@ -946,8 +1012,37 @@ k_ac_stage_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf
     }
 }
 
+// The learned-curvature pass of one or many boxes ahead of their step, on the
+// same persistent queue and work items (buf[b].phin: phi^n; buf[b].mlpy and
+// buf[b].mlpf: the network outputs and flags the step reads).
+template <int TW, bool FX>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_mlp_pass_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+                 int nbox, uint32_t *counter, int parity)
+{
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.y * TW + threadIdx.x;
+    const uint32_t total = first[nbox];
+    if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[parity], 1u);
+        __syncthreads();
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        step_tile<0, true, false, true, TW, true, FX, false, false, true>(tab[b], buf[b], item - first[b]);
+    }
+}
+
 template <int S, bool TP, bool FRC, bool ML, int TW, bool FX, bool PH>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(ML ? 1 : 3)))
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
              int nbox, uint32_t *counter, int parity)
 {
