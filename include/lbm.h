@@ -132,7 +132,9 @@ size_t lbm_workspace_bytes(const lbm_config *cfg);
 int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_bytes, const double *d_phi0,
              const double *d_u0, const double *d_pstar0, void *stream);
 
-/* Advance nsteps >= 0 time steps (one fused kernel launch per step). */
+/* Advance nsteps >= 0 time steps: one fused kernel launch per step, plus the
+ * learned-curvature network pass ahead of it (LBM_CURV_MLP) and two more
+ * phase-field stages after it (ac_rk3); pairs of steps replay a captured graph. */
 int lbm_step(lbm_handle *h, int64_t nsteps);
 
 /* Fields at the current time n, written to caller device buffers; any pointer
