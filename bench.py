@@ -305,8 +305,8 @@ def hit_report(steps=20000, every=2000, n=256, oracle_n=64, oracle_checks=(250, 
 
 
 def oracle_timing():
-    """The FP64 oracle on the host cores for the four workloads (BASELINE
-    configs 1-4): TGV 32^3 (200 steps), static droplet 64^3 (R = 12, ratio 10;
+    """The FP64 oracle on the host cores for the four benchmark workloads:
+    TGV 32^3 (200 steps), static droplet 64^3 (R = 12, ratio 10;
     the first 500 of its 5000 steps), single-phase forced HIT 256^3 (20 steps),
     512^3 bubbly HIT (2 steps).  Prints one line per workload as it finishes
     and returns MLUPS per workload."""
