@@ -29,7 +29,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], stage[2], mlpy, mlpf, frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
+    size_t f[2], phi[2], u[2], stage[2], mlpy, frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -53,11 +53,10 @@ Layout layout_of(const lbm_config &c)
     } else {
         L.phi[0] = L.phi[1] = L.u[0] = L.u[1] = (size_t)-1;
     }
-    if (c.two_phase && c.curv_mode == LBM_CURV_MLP) {  // network outputs and selection flags
+    if (c.two_phase && c.curv_mode == LBM_CURV_MLP) {  // network outputs at the interface cells
         L.mlpy = take(16 * N);
-        L.mlpf = take(N);
     } else {
-        L.mlpy = L.mlpf = (size_t)-1;
+        L.mlpy = (size_t)-1;
     }
     if (c.two_phase && c.ac_rk3) {  // the two intermediate Runge-Kutta stages of phi
         L.stage[0] = take(8 * N);
@@ -191,7 +190,6 @@ struct lbm_handle {
     void *phi(int k) { return cfg.two_phase ? (void *)(ws + L.phi[k]) : nullptr; }
     void *stage(int k) { return cfg.two_phase && cfg.ac_rk3 ? (void *)(ws + L.stage[k]) : nullptr; }
     void *mlpy() { return cfg.two_phase && cfg.curv_mode == LBM_CURV_MLP ? (void *)(ws + L.mlpy) : nullptr; }
-    void *mlpf() { return cfg.two_phase && cfg.curv_mode == LBM_CURV_MLP ? (void *)(ws + L.mlpf) : nullptr; }
     float *u(int k) { return cfg.two_phase ? (float *)(ws + L.u[k]) : nullptr; }
 
     int fail(int code, const std::string &msg)
@@ -607,10 +605,10 @@ int batch_upload(lbm_batch *b)
             // with the Runge-Kutta update the step's own Euler update of phi
             // is the first stage (into stage 0); stages 2 and 3 follow
             buf[(size_t)p * n + i] = lbm::Buffers{h->f(c), h->f(o), h->phi(c), b->rk3 ? h->stage(0) : h->phi(o),
-                                                  h->u(c), h->u(o), nullptr, h->mlpy(), h->mlpf()};
+                                                  h->u(c), h->u(o), nullptr, h->mlpy()};
             if (b->ml)
                 buf[(size_t)(6 + p) * n + i] =
-                    lbm::Buffers{nullptr, nullptr, h->phi(c), nullptr, nullptr, nullptr, nullptr, h->mlpy(), h->mlpf()};
+                    lbm::Buffers{nullptr, nullptr, h->phi(c), nullptr, nullptr, nullptr, nullptr, h->mlpy()};
             if (b->rk3) {
                 buf[(size_t)(2 + p) * n + i] =
                     lbm::Buffers{nullptr, nullptr, h->stage(0), h->stage(1), h->u(c), nullptr, h->phi(c)};

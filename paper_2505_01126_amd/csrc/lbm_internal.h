@@ -69,8 +69,8 @@ struct Buffers {
     const float *uin;
     float *uout;
     const void *phin0;  // phi^n for the Runge-Kutta stages of the phase field
-    void *mlpy;         // learned curvature: network outputs (float4 per site)
-    void *mlpf;         // and selection flags (one byte per site), from the pass before the step
+    void *mlpy;         // learned curvature: network outputs (float4 per site; NaN at the
+                        // interface cells the criterion does not select), from the pass before the step
 };
 
 hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,

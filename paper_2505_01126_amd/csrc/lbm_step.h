@@ -573,12 +573,13 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
 {
     static_assert(!ACO || (TP && !FX && !ML), "a Runge-Kutta stage needs the FP64 phase field");
     static_assert(!PRE || (TP && ML && !ACO), "the network pass belongs to the learned curvature");
-    // PRE: the learned-curvature pass that runs before the step: for every
-    // interface cell that the curvature criterion selects, the network output
-    // goes to B.mlpy (float4 per site) and a flag to B.mlpf (one byte per site,
-    // 0 or 1 for every site); nothing else.  The step with ML set then reads
-    // the flag and, where it is set, the output, so the network's registers and
-    // LDS are not part of the step kernel.
+    // PRE: the learned-curvature pass that runs before the step: at every
+    // interface cell (0.02 < phi < 0.98) it leaves in B.mlpy (float4 per site)
+    // the network output where the curvature criterion selects the cell and
+    // NaN elsewhere; nothing else.  The step with ML set reads it where its own
+    // criterion selects the cell (the same test on the same stencil, so the
+    // pass has written there) and falls back to finite differences on NaN, so
+    // the network's registers and LDS are not part of the step kernel.
     constexpr bool NET = ML && PRE;  // the network is evaluated in this kernel
     constexpr bool LBM = !ACO && !PRE;  // the populations are streamed and collided
     using T = typename Pop<S>::T;
@@ -683,7 +684,6 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     float f_ul[FROUNDS], f_ur[FROUNDS];  // prefetched face velocities
     float jz_left = 0.f, uz_c = 0.f, uz_n = 0.f;
     PT po = 0;              // prefetched own phi
-    uint32_t mflag = 0;     // learned curvature: prefetched selection flag of the own site
 
     auto fetch_plane = [&](int z) {
         const LBM_GLOBAL PT *src = phin + (size_t)modi(z, nz) * plane;
@@ -798,7 +798,6 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
             uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
             po = phin[(size_t)z0 * plane + own_xy];
-            if constexpr (ML) mflag = gconst((const uint8_t *)B.mlpf)[(size_t)z0 * plane + own_xy];
             float v[6];
 #pragma unroll
             for (int k = 0; k < 6; k++) v[k] = sphi[ring(z0 - 3 + k)][lc];
@@ -847,15 +846,13 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                 }
                 mlp_wave(smw, smwave[tid >> 6], sel, ph, y, tid & 63);
             }
-            if (active) {
-                gmut((uint8_t *)B.mlpf)[own] = sel ? 1 : 0;
-                if (sel) {
-                    LBM_GLOBAL float *yo = gmut((float *)B.mlpy) + 4 * (size_t)own;
-                    yo[0] = y[0];
-                    yo[1] = y[1];
-                    yo[2] = y[2];
-                    yo[3] = y[3];
-                }
+            if (cand) {
+                const float nan = __builtin_nanf("");
+                LBM_GLOBAL float *yo = gmut((float *)B.mlpy) + 4 * (size_t)own;
+                yo[0] = sel ? y[0] : nan;
+                yo[1] = sel ? y[1] : nan;
+                yo[2] = sel ? y[2] : nan;
+                yo[3] = sel ? y[3] : nan;
             }
             continue;
         }
@@ -935,9 +932,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         float fs[3] = {0.f, 0.f, 0.f};
         if constexpr (ML) {
             if (active) {
-                const uint32_t use = mflag;
-                if (more) mflag = gconst((const uint8_t *)B.mlpf)[(size_t)own + plane];  // next plane's
-                if (use) {
+                if (sel) {
                     const LBM_GLOBAL float *yi = gconst((const float *)B.mlpy) + 4 * (size_t)own;
                     const float y[4] = {yi[0], yi[1], yi[2], yi[3]};
                     surface_blend(G, P, kfd, gn, y, fs);
@@ -1013,8 +1008,8 @@ k_ac_stage_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf
 }
 
 // The learned-curvature pass of one or many boxes ahead of their step, on the
-// same persistent queue and work items (buf[b].phin: phi^n; buf[b].mlpy and
-// buf[b].mlpf: the network outputs and flags the step reads).
+// same persistent queue and work items (buf[b].phin: phi^n; buf[b].mlpy: the
+// network outputs the step reads).
 template <int TW, bool FX>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_mlp_pass_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
