@@ -6,7 +6,7 @@ on the z-chunk length or on which workgroup takes an item.  Covered: uneven
 and ragged box shapes, different physical parameters per box, odd and even
 step counts (graph replays of step pairs plus single launches), FD and learned
 curvature, members stepped on their own between batch steps, the autotuner,
-and rejected mixes.  One member is also checked against the FP64 oracle.
+cached and non-temporal output stores, and rejected mixes.  One member is also checked against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -16,7 +16,10 @@ from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 20, 70), (32, 32, 32), (40, 24, 48), (20, 36, 20), (24, 8, 96)]
+# the last box's rows fill whole 128-byte lines (nx = 128): alone (tile 64) its
+# outputs are stored with the non-temporal policy, in a batch with 16-bit
+# storage and tile 32 with the default one; the fields must not differ
+SHAPES = [(16, 20, 70), (32, 32, 32), (40, 24, 48), (20, 36, 20), (24, 8, 96), (16, 12, 128)]
 
 
 def _boxes(storage, curv, seed=0):
