@@ -434,8 +434,6 @@ def main():
                          "against the oracle over time) and exit")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle on the four workloads (several minutes of CPU) and exit")
-    ap.add_argument("--bandwidth-probe", action="store_true",
-                    help="only run the streaming-kernel bandwidth probe (copy, read, write, 27-row) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 10 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -453,15 +451,6 @@ def main():
             pass
         print(json.dumps(res), flush=True)
         return
-
-    if args.bandwidth_probe:
-        import subprocess
-
-        probe = os.path.join(ROOT, "paper_2505_01126_amd", "bw_probe")
-        if not os.path.exists(probe):
-            print("bench.py: bw_probe is not built (run __graft_entry__.build())", file=sys.stderr)
-            sys.exit(1)
-        sys.exit(subprocess.call([probe]))
 
     import torch
 

@@ -32,10 +32,15 @@
  * moments, collision invariants and the closed-form a^(2), stencil exactness
  * on polynomials, WENO-5 order, the steady tanh profile and its translation,
  * Taylor-Green and ABC decay, conservation, Laplace's law, fp16 rounding, the
- * network's identity reduction and its gradient against finite differences.
- * Parity unpinned: the viscous correction F^nu (it vanishes at rest and in
- * uniform density; no closed form isolates it) and the one-step lag of the
- * Allen-Cahn velocity (a reading of the time integration, not a closed form).
+ * network's identity reduction and its gradient against finite differences;
+ * the initial non-equilibrium part against the shear-wave closed form; every
+ * branch of the learned-curvature blend against a constant-output network;
+ * the viscous correction F^nu and the phase-dependent relaxation time through
+ * the steady layered flow of a variable-property momentum equation.  Several
+ * of these tests compile a copy of this file with a planted mistake and show
+ * that the pin catches it.
+ * Parity unpinned: the one-step lag of the Allen-Cahn velocity (a reading of
+ * the time integration, not a closed form).
  */
 #include "oracle.h"
 

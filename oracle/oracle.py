@@ -31,49 +31,57 @@ class _Params(C.Structure):
 
 
 def lib():
+    """The oracle library (built on first use)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIBPATH):
             from .build import build
             build()
-        L = C.CDLL(LIBPATH)
-        dp = C.POINTER(C.c_double)
-        L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.POINTER(_Params), dp, dp, dp]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_step.argtypes = [C.c_void_p, C.c_long]
-        L.orc_moments.argtypes = [C.c_void_p, dp, dp, dp, dp]
-        L.orc_reduce.argtypes = [C.c_void_p, dp]
-        L.orc_get_f.argtypes = [C.c_void_p, dp]
-        L.orc_set_f.argtypes = [C.c_void_p, dp]
-        L.orc_get_uprev.argtypes = [C.c_void_p, dp]
-        L.orc_set_aext.argtypes = [C.c_void_p, dp]
-        L.orc_forcing_window.argtypes = [dp] + [C.c_int] * 10 + [dp]
-        L.orc_steps_done.argtypes = [C.c_void_p]
-        L.orc_steps_done.restype = C.c_long
-        L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp]
-        L.orc_feq.argtypes = [C.c_double, dp, dp]
-        L.orc_guo.argtypes = [dp, dp, dp]
-        L.orc_collide.argtypes = [dp, dp, dp, C.c_double, dp, dp]
-        for name in ("orc_gradient", "orc_hessian", "orc_laplacian"):
-            getattr(L, name).argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
-        L.orc_curvature.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp]
-        L.orc_weno5.restype = C.c_double
-        L.orc_weno5.argtypes = [C.c_double] * 5
-        L.orc_ac_update.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp]
-        L.orc_threads.restype = C.c_int
-        L.orc_to_half.restype = C.c_double
-        L.orc_to_half.argtypes = [C.c_double]
-        L.orc_mlp_set_fp16.argtypes = [C.c_int]
-        L.orc_mlp_forward.argtypes = [dp, dp, C.c_long, dp]
-        L.orc_mlp_loss_grad.restype = C.c_double
-        L.orc_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_long, dp]
-        L.orc_adam.argtypes = [dp, dp, dp, dp, C.c_long, C.c_long, C.c_double, C.c_double, C.c_double,
-                               C.c_double, dp]
-        L.orc_harvest.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, dp, C.c_long,
-                                  C.POINTER(C.c_long)]
-        _lib = L
+        _lib = load(LIBPATH)
     return _lib
+
+
+def load(path):
+    """Load and bind a build of oracle.c.  Tests that plant a mistake in a
+    copy of the oracle (to show that a pin catches it) pass that build to
+    `Oracle(..., library=load(path))`."""
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.POINTER(_Params), dp, dp, dp]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_long]
+    L.orc_moments.argtypes = [C.c_void_p, dp, dp, dp, dp]
+    L.orc_reduce.argtypes = [C.c_void_p, dp]
+    L.orc_get_f.argtypes = [C.c_void_p, dp]
+    L.orc_set_f.argtypes = [C.c_void_p, dp]
+    L.orc_get_uprev.argtypes = [C.c_void_p, dp]
+    L.orc_set_aext.argtypes = [C.c_void_p, dp]
+    L.orc_forcing_window.argtypes = [dp] + [C.c_int] * 10 + [dp]
+    L.orc_steps_done.argtypes = [C.c_void_p]
+    L.orc_steps_done.restype = C.c_long
+    L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp]
+    L.orc_feq.argtypes = [C.c_double, dp, dp]
+    L.orc_guo.argtypes = [dp, dp, dp]
+    L.orc_collide.argtypes = [dp, dp, dp, C.c_double, dp, dp]
+    for name in ("orc_gradient", "orc_hessian", "orc_laplacian"):
+        getattr(L, name).argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
+    L.orc_curvature.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp]
+    L.orc_weno5.restype = C.c_double
+    L.orc_weno5.argtypes = [C.c_double] * 5
+    L.orc_ac_update.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp]
+    L.orc_threads.restype = C.c_int
+    L.orc_to_half.restype = C.c_double
+    L.orc_to_half.argtypes = [C.c_double]
+    L.orc_mlp_set_fp16.argtypes = [C.c_int]
+    L.orc_mlp_forward.argtypes = [dp, dp, C.c_long, dp]
+    L.orc_mlp_loss_grad.restype = C.c_double
+    L.orc_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_long, dp]
+    L.orc_adam.argtypes = [dp, dp, dp, dp, C.c_long, C.c_long, C.c_double, C.c_double, C.c_double,
+                           C.c_double, dp]
+    L.orc_harvest.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, dp, C.c_long,
+                              C.POINTER(C.c_long)]
+    return L
 
 
 def _p(a):
@@ -221,7 +229,8 @@ class Oracle:
 
     def __init__(self, shape, tau, phi0=None, u0=None, pstar0=None, two_phase=None, rho_l=1.0, rho_g=1.0,
                  sigma=0.0, mobility=0.0, width=4.0, p0=1.0, modes=None, curv_mode=0, k_lo=0.4, k_hi=0.6,
-                 mlp=None, gravity=(0.0, 0.0, 0.0), tau_g=0.0, ac_rk3=False):
+                 mlp=None, gravity=(0.0, 0.0, 0.0), tau_g=0.0, ac_rk3=False, library=None):
+        self._L = library if library is not None else lib()
         nz, ny, nx = shape
         self.shape = tuple(shape)
         self.N = nx * ny * nz
@@ -235,7 +244,7 @@ class Oracle:
         self._phi0 = _f64(phi0)
         self._u0 = _f64(u0)
         self._ps0 = _f64(pstar0)
-        h = lib().orc_create(C.byref(prm), _p(self._phi0), _p(self._u0), _p(self._ps0))
+        h = self._L.orc_create(C.byref(prm), _p(self._phi0), _p(self._u0), _p(self._ps0))
         if not h:
             raise ValueError("oracle: invalid parameters")
         self._h = C.c_void_p(h)
@@ -244,45 +253,45 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     def step(self, n=1):
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
 
     @property
     def steps(self):
-        return lib().orc_steps_done(self._h)
+        return self._L.orc_steps_done(self._h)
 
     def moments(self):
         rho = np.zeros(self.shape)
         p = np.zeros(self.shape)
         u = np.zeros((3,) + self.shape)
         phi = np.zeros(self.shape)
-        lib().orc_moments(self._h, _p(rho), _p(p), _p(u), _p(phi))
+        self._L.orc_moments(self._h, _p(rho), _p(p), _p(u), _p(phi))
         return {"rho": rho, "p": p, "u": u, "phi": phi}
 
     def reduce(self):
         out = np.zeros(NRED)
-        lib().orc_reduce(self._h, _p(out))
+        self._L.orc_reduce(self._h, _p(out))
         return out
 
     def get_f(self):
         f = np.zeros((27,) + self.shape)
-        lib().orc_get_f(self._h, _p(f))
+        self._L.orc_get_f(self._h, _p(f))
         return f
 
     def set_f(self, f):
         f = _f64(f)
-        lib().orc_set_f(self._h, _p(f))
+        self._L.orc_set_f(self._h, _p(f))
 
     def set_accel(self, a):
         """Replace the body acceleration field ([3, nz, ny, nx])."""
         self._aext = _f64(a)
         assert self._aext.size == 3 * self.N
-        lib().orc_set_aext(self._h, _p(self._aext))
+        self._L.orc_set_aext(self._h, _p(self._aext))
 
     def get_uprev(self):
         u = np.zeros((3,) + self.shape)
-        lib().orc_get_uprev(self._h, _p(u))
+        self._L.orc_get_uprev(self._h, _p(u))
         return u

@@ -7,7 +7,6 @@ import tempfile
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
-PROBE = os.path.join(PKG, "bw_probe")  # standalone bandwidth probe (not part of the library)
 SOURCES = ["lbm_step_s0.hip", "lbm_step_s1.hip", "lbm_step_s2.hip", "lbm_kernels.hip", "lbm_mlp.hip", "lbm_api.hip"]
 
 HIPCC_FLAGS = [
@@ -41,12 +40,6 @@ def build(verbose=False, extra=None):
             print(" ".join(link), flush=True)
         subprocess.check_call(link)
     os.replace(tmp, LIB)
-    probe = [hipcc] + [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")] + [
-        "-o", PROBE + ".tmp", os.path.join(PKG, "csrc", "bw_probe.hip")]
-    if verbose:
-        print(" ".join(probe), flush=True)
-    subprocess.check_call(probe)
-    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

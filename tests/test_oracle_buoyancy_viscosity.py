@@ -133,7 +133,11 @@ def _steady_profile(phi_y, rho_l, rho_g, nu_l, nu_g, amp, refine=16):
     return u[::refine]
 
 
-def test_layered_kolmogorov_flow_matches_variable_property_momentum_equation():
+def _layered_flow(library=None):
+    """Steady layered Kolmogorov flow of the oracle (liquid slab in gas,
+    density ratio 10, tau 1.0 / 0.7, a_x = amp sin(2 pi y / L), 6000 steps)
+    against the independent fine-grid solution: (max relative u_x error,
+    max |u_y| over max |u_ref|)."""
     shape = (4, 32, 4)
     L = shape[1]
     y = np.arange(L, dtype=np.float64)
@@ -143,13 +147,37 @@ def test_layered_kolmogorov_flow_matches_variable_property_momentum_equation():
     tau_l, tau_g, rho_l, rho_g, amp = 1.0, 0.7, 1.0, 0.1, 2e-6
     modes = np.array([[0, 1, 0, 0.0, -amp, 0, 0, 0, 0]], dtype=np.float64)  # a_x = amp sin(2 pi y / L)
     o = O.Oracle(shape, tau_l, phi0=phi0, rho_l=rho_l, rho_g=rho_g, sigma=0.0, mobility=0.05, width=4.0, p0=0.0,
-                 modes=modes, tau_g=tau_g)
+                 modes=modes, tau_g=tau_g, library=library)
     o.step(6000)
     m = o.moments()
     ux = m["u"][0][0, :, 0]
     phi_end = m["phi"][0, :, 0]
     ref = _steady_profile(phi_end, rho_l, rho_g, (tau_l - 0.5) / 3.0, (tau_g - 0.5) / 3.0, amp)
     err = np.abs(ux - ref).max() / np.abs(ref).max()
-    print(f"layered flow: max |u| {np.abs(ref).max():.4e}, rel err {err:.3e}")
-    assert np.abs(m["u"][1]).max() < 1e-6 * np.abs(ref).max()
+    return err, np.abs(m["u"][1]).max() / np.abs(ref).max()
+
+
+def test_layered_kolmogorov_flow_matches_variable_property_momentum_equation():
+    """This also pins the viscous correction F^nu of Eq. (8): without it the
+    steady profile moves far outside the bar (next test)."""
+    err, uy = _layered_flow()
+    print(f"layered flow: rel err {err:.3e}")
+    assert uy < 1e-6
     assert err < 2e-2
+
+
+PLANTED_VISCOUS = {
+    "no viscous correction F^nu": ("Fnu *= -(nu / (tau * CS2));", "Fnu *= 0.0;"),
+    "F^nu with the wrong sign": ("Fnu *= -(nu / (tau * CS2));", "Fnu *= (nu / (tau * CS2));"),
+    "one relaxation time": ("return c * p->tau + (1.0 - c) * p->tau_g;", "return p->tau;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PLANTED_VISCOUS))
+def test_planted_viscous_mistake_is_caught(name, tmp_path):
+    from oracle import build as OB
+
+    lib = O.load(OB.build_planted([PLANTED_VISCOUS[name]], str(tmp_path)))
+    err, uy = _layered_flow(lib)
+    print(f"{name}: rel err {err:.3e}")
+    assert err > 2e-2
