@@ -694,8 +694,12 @@ static void site_macro(const orc_state *s, long x, long y, long z, const double 
         Fs[a] = -1.5 * p->width * p->sigma * K * g2 * ns[a]; /* -(3 delta/2) sigma K |g|^2 n_s */
         grho[a] = (p->rho_l - p->rho_g) * g[a];
         Fp[a] = -pstar * CS2 * grho[a];
-        /* body force, plus buoyancy against the box-mean hydrostatic balance */
-        Fb[a] = rho * s->aext[a * N + st] + (rho - s->rho_mean) * p->gravity[a];
+        /* body force, plus buoyancy against the box-mean hydrostatic balance
+           (absent, not multiplied by zero, without gravity: a non-finite site
+           would otherwise reach every site through the box mean) */
+        Fb[a] = rho * s->aext[a * N + st];
+        if (p->gravity[a] != 0.0)
+            Fb[a] += (rho - s->rho_mean) * p->gravity[a];
         u0[a] = j[a] + (Fs[a] + Fp[a] + Fb[a]) / (2.0 * rho);
     }
     /* viscous correction with the non-equilibrium stress at u0 */

@@ -27,3 +27,20 @@ def test_reductions_equal_numpy_statistics_of_the_fields():
     for k in range(10):
         assert r[k] == pytest.approx(expect[k], rel=1e-12, abs=1e-15), k
     assert r[8] > 0.0
+
+
+def test_nonfinite_count_is_the_stencil_support_of_a_nan():
+    """One NaN in phi0: the forces of Eq. (8) use g and H of the 27-point
+    stencil, so the velocity of exactly the 3^3 sites around it is NaN at t = 0
+    (and phi at the site itself): out[9] = 27, and the other statistics skip
+    those sites and stay finite."""
+    shape = (12, 13, 14)
+    phi0, _ = I.droplet(shape, 4.0, 4.0, seed=8)
+    phi0[3, 4, 5] = np.nan
+    o = O.Oracle(shape, 0.8, phi0=phi0, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    r = o.reduce()
+    assert r[9] == 27
+    assert np.all(np.isfinite(r[:9]))
+    u = o.moments()["u"]
+    bad = ~np.isfinite(u).all(0)
+    assert bad.sum() == 27 and bad[2:5, 3:6, 4:7].all()
