@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import check
 from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -133,10 +134,7 @@ def test_batch_member_matches_oracle():
     o.step(10)
     mo = o.moments()
     m = {k: v.double().cpu().numpy() for k, v in members[2].moments().items()}
-    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
-    print(f"batch member vs oracle: u rel err {e:.3e}")
-    assert e < 1e-5
-    assert np.abs(m["phi"] - mo["phi"]).max() < 1e-5
+    check(m, mo, "f32", "batch member vs oracle", phi_bar=1e-5, drho=1.0)
     b.close()
 
 

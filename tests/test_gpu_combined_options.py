@@ -7,14 +7,16 @@
 * a batch of boxes with buoyancy and a viscosity contrast, bit-identical to
   the boxes stepped alone, and a batch that mixes them with plain boxes is
   rejected.
-Bars as for the single options: u relative L2 below 1e-5 (FP32 populations;
-1e-3 where the learned curvature's fp16 rounding of activations can flip),
-phi within 1e-5.
+Bars as for the single options (tests/parity.py): u relative L2 and max |du| /
+max |u_o| below 1e-5 with FP32 populations, plus, with the learned curvature,
+2^-10 of the network's share of the flow (its fp16 roundings can land one
+unit apart); p against the oracle's pressure variation; phi within 1e-5.
 """
 import numpy as np
 import pytest
 
 import oracle as O
+from parity import check
 from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -51,11 +53,14 @@ def test_learned_curvature_buoyancy_viscosity_runge_kutta():
     o = O.Oracle(shape, 0.8, curv_mode=1, mlp=w, ac_rk3=True, **kw)
     o.step(40)
     mo = o.moments()
-    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
-    dphi = np.abs(m["phi"] - mo["phi"]).max()
-    print(f"mlp + buoyancy + tau_g + rk3: u rel err {e:.3e}, phi max abs {dphi:.3e}")
-    assert e < 1e-3
-    assert dphi < 1e-5
+    # the network's share of the flow carries the fp16-rounding floor of the
+    # learned-curvature step (2^-10 of that share, as in tests/test_gpu_mlp.py)
+    ofd = O.Oracle(shape, 0.8, ac_rk3=True, **kw)
+    ofd.step(40)
+    dfd = np.linalg.norm(ofd.moments()["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    bar = 1e-5 + 2.0 ** -10 * dfd
+    print(f"mlp + buoyancy + tau_g + rk3: FD vs learned oracle runs differ by {dfd:.3e}; u bar {bar:.3e}")
+    check(m, mo, "f32", "mlp + buoyancy + tau_g + rk3", u_bar=bar, p_bar=bar, phi_bar=1e-5, drho=0.9)
     assert abs(r1[0] - r0[0]) / r0[0] < 1e-12
 
 
@@ -77,11 +82,8 @@ def test_fixed_point_phi_with_buoyancy():
     o = O.Oracle(shape, 0.8, **kw)
     o.step(100)
     mo = o.moments()
-    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
-    dphi = np.abs(m["phi"] - mo["phi"]).max()
-    print(f"fix32 + buoyancy: u rel err {e:.3e}, phi max abs {dphi:.3e}, sum phi {r[0]!r} vs {expect!r}")
-    assert e < 1e-5
-    assert dphi < 1e-5
+    check(m, mo, "f32", "fix32 + buoyancy", phi_bar=1e-5, drho=0.9)
+    print(f"fix32 + buoyancy: sum phi {r[0]!r} vs {expect!r}")
     assert r[0] == expect
 
 

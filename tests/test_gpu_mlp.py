@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import check
 from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -167,11 +168,16 @@ def test_step_with_learned_curvature_matches_oracle():
     o = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, curv_mode=1, mlp=w, **kw)
     o.step(30)
     mo = o.moments()
-    e = np.linalg.norm(m["u"] - mo["u"]) / np.linalg.norm(mo["u"])
     # the learned force differs from the finite-difference one (the test is not vacuous)
     ofd = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, **kw)
     ofd.step(30)
     dfd = np.linalg.norm(ofd.moments()["u"] - mo["u"]) / np.linalg.norm(mo["u"])
-    print(f"learned-curvature step: u rel err {e:.3e} (FD vs learned oracle runs differ by {dfd:.3e})")
+    # Both sides round the network's input, hidden activations and weights to
+    # fp16, but form the sums in FP32 (MFMA) and FP64: a rounding to fp16 can
+    # land one unit apart (2^-11 relative, two roundings in a row: 2^-10), so
+    # the network's part of the flow, dfd, carries a relative error of up to
+    # 2^-10 on top of the FP32 bar of the finite-difference path.
+    bar = 1e-5 + 2.0 ** -10 * dfd
+    print(f"learned-curvature step: FD vs learned oracle runs differ by {dfd:.3e}; u bar {bar:.3e}")
+    check(m, mo, "f32", "learned-curvature step", u_bar=bar, p_bar=bar, phi_bar=1e-5, drho=0.9)
     assert dfd > 1e-3
-    assert e < 1e-3

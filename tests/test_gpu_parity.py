@@ -1,8 +1,9 @@
 """GPU (HIP, gfx950) lattice update against the FP64 oracle on identical seeded inputs.
 
-Error metric (velocity): relative L2 norm ||u_gpu - u_oracle|| / ||u_oracle||
-over all sites and components.  Bars: 1e-5 with FP32 storage, 1e-3 with FP16
-storage; BF16 storage (8-bit mantissa) is held to 1e-2.  Sizes are ragged
+Every case compares u, p, rho (and phi) element by element (tests/parity.py):
+relative L2 and max |du| / max |u_o| of the velocity below 1e-5 with FP32
+storage, 1e-3 with FP16 storage, 1e-2 with BF16 (8-bit mantissa), and p
+within its bar against the oracle's pressure variation.  Sizes are ragged
 against the 64 x 4 workgroup tile and the z-chunk so that edge tiles, periodic
 wrap inside the tile and several workgroups are all exercised.
 """
@@ -11,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2505_01126_amd import inputs as I
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -19,10 +21,6 @@ def _lbm():
     from paper_2505_01126_amd import lbm
 
     return lbm
-
-
-def relerr(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def both(shape, tau, steps, storage="f32", zchunk=0, **kw):
@@ -45,20 +43,17 @@ def test_initial_fields_match_oracle():
     phi0, _ = I.droplet(shape, 6.0, 4.0, seed=1)
     u0 = I.random_u(shape, 0.02, seed=2)
     m, r, mo, ro = both(shape, 0.7, 0, phi0=phi0, u0=u0, zchunk=8, **TWO_PHASE)
-    assert relerr(m["u"], mo["u"]) < 1e-6
+    check(m, mo, "f32", "initial fields", u_bar=1e-6, phi_bar=1e-300, drho=0.9)
     np.testing.assert_array_equal(m["phi"], mo["phi"])
     # p* = 0 in this gauge: only FP32 round-off of the non-equilibrium part remains
     assert np.abs(m["p"] - mo["p"]).max() < 1e-9
-    assert relerr(m["rho"], mo["rho"]) < 1e-6
 
 
 def test_tgv_parity_fp32():
     shape = (32, 32, 32)
     u0, p0, _ = I.tgv(shape)
     m, r, mo, ro = both(shape, 0.8, 200, u0=u0, pstar0=p0, p0=1.0)
-    e = relerr(m["u"], mo["u"])
-    print("TGV fp32 rel err", e)
-    assert e < 1e-5
+    check(m, mo, "f32", "TGV 32^3, 200 steps")
 
 
 def test_forced_single_phase_ragged_fp32():
@@ -66,9 +61,7 @@ def test_forced_single_phase_ragged_fp32():
     u0 = I.solenoidal_field(shape, rms=0.02, k0=2.0, seed=5)
     modes = I.forcing_modes(1e-5, seed=6)
     m, r, mo, ro = both(shape, 0.6, 100, zchunk=8, u0=u0, modes=modes, p0=1.0)
-    e = relerr(m["u"], mo["u"])
-    print("forced rel err", e)
-    assert e < 1e-5
+    check(m, mo, "f32", "forced single phase, ragged")
     np.testing.assert_allclose(r[2], ro[2], rtol=1e-6)
 
 
@@ -77,10 +70,7 @@ def test_two_phase_parity_ragged_fp32():
     phi0, _ = I.droplet(shape, 6.0, 4.0, seed=3)
     u0 = I.random_u(shape, 0.01, seed=4)
     m, r, mo, ro = both(shape, 0.8, 100, zchunk=8, phi0=phi0, u0=u0, **TWO_PHASE)
-    e = relerr(m["u"], mo["u"])
-    print("two-phase rel err", e, "phi max abs", np.abs(m["phi"] - mo["phi"]).max())
-    assert e < 1e-5
-    assert np.abs(m["phi"] - mo["phi"]).max() < 1e-5
+    check(m, mo, "f32", "two phase, ragged", phi_bar=1e-5, drho=0.9)
     assert abs(r[0] - ro[0]) / ro[0] < 1e-13
 
 
@@ -90,19 +80,15 @@ def test_two_phase_forced_fp32():
     u0 = I.solenoidal_field(shape, rms=0.01, k0=2.0, seed=8)
     modes = I.forcing_modes(1e-5, seed=9)
     m, r, mo, ro = both(shape, 0.6, 60, zchunk=5, phi0=phi0, u0=u0, modes=modes, **TWO_PHASE)
-    e = relerr(m["u"], mo["u"])
-    print("two-phase forced rel err", e)
-    assert e < 1e-5
+    check(m, mo, "f32", "two phase, forced", phi_bar=1e-5, drho=0.9)
 
 
-@pytest.mark.parametrize("storage,bar", [("f16", 1e-3), ("bf16", 1e-2)])
-def test_tgv_parity_half_storage(storage, bar):
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_tgv_parity_half_storage(storage):
     shape = (32, 32, 32)
     u0, p0, _ = I.tgv(shape)
     m, r, mo, ro = both(shape, 0.8, 200, storage=storage, u0=u0, pstar0=p0, p0=1.0)
-    e = relerr(m["u"], mo["u"])
-    print(f"TGV {storage} rel err", e)
-    assert e < bar
+    check(m, mo, storage, "TGV 32^3, 200 steps")
 
 
 def test_reductions_match_oracle():
@@ -110,6 +96,7 @@ def test_reductions_match_oracle():
     phi0, _ = I.droplet(shape, 5.0, 4.0, seed=11)
     u0 = I.random_u(shape, 0.01, seed=12)
     m, r, mo, ro = both(shape, 0.9, 20, phi0=phi0, u0=u0, **TWO_PHASE)
+    check(m, mo, "f32", "reductions case", phi_bar=1e-5, drho=0.9)
     np.testing.assert_allclose(r[0], ro[0], rtol=1e-12)
     np.testing.assert_allclose(r[1], ro[1], rtol=1e-7)
     np.testing.assert_allclose(r[3:6], ro[3:6], rtol=1e-4, atol=1e-7 * abs(ro[6]) ** 0.5 * shape[0] * 10)
@@ -147,8 +134,24 @@ def test_bulk_planes_match_oracle_and_conserve():
     u0 = I.solenoidal_field(shape, rms=0.01, k0=2.0, seed=22)
     modes = I.forcing_modes(1e-5, seed=23)
     m, r, mo, ro = both(shape, 0.6, 40, zchunk=16, phi0=phi0, u0=u0, modes=modes, **TWO_PHASE)
-    e = relerr(m["u"], mo["u"])
-    print("bulk-path rel err", e, "phi max abs", np.abs(m["phi"] - mo["phi"]).max())
-    assert e < 1e-5
-    assert np.abs(m["phi"] - mo["phi"]).max() < 1e-5
+    check(m, mo, "f32", "bulk planes", phi_bar=1e-5, drho=0.9)
     assert abs(r[0] - ro[0]) / ro[0] < 1e-13
+
+
+def test_nonfinite_sites_are_counted():
+    """A NaN in phi0 at one site reaches the velocity of exactly the 27 sites
+    whose phase-field stencil holds it (through g and H in the forces), so
+    lbm_reduce's out[9] counts 27 at t = 0, as the oracle's does, and the other
+    statistics stay finite (they skip those sites)."""
+    lbm = _lbm()
+    shape = (16, 16, 24)
+    phi0, _ = I.droplet(shape, 5.0, 4.0, seed=13)
+    phi0[5, 7, 9] = np.nan
+    print("case NaN in phi0 at (z, y, x) = (5, 7, 9)", flush=True)
+    g = lbm.Lattice(shape, 0.8, phi0=phi0, **TWO_PHASE)
+    r = g.reduce()
+    g.close()
+    ro = O.Oracle(shape, 0.8, phi0=phi0, **TWO_PHASE).reduce()
+    print("non-finite sites: GPU", r[9], "oracle", ro[9])
+    assert ro[9] == 27 and r[9] == 27
+    assert np.all(np.isfinite(r[:9]))
