@@ -251,11 +251,16 @@ static double lap_at(int nx, int ny, int nz, const double *psi, long x, long y, 
     return 2.0 * s / CS2;
 }
 
+/* Loops over the sites of boxes below this size run on one thread: the
+   thread start-up of each parallel loop would cost more than the loop. */
+#define ORC_PAR_MIN 32768L
+static int orc_par(long n) { return n >= ORC_PAR_MIN; }
+
 void orc_gradient(int nx, int ny, int nz, const double *psi, double *grad)
 {
     lattice_init();
     long N = (long)nx * ny * nz;
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -271,7 +276,7 @@ void orc_hessian(int nx, int ny, int nz, const double *psi, double *hess)
 {
     lattice_init();
     long N = (long)nx * ny * nz;
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -286,7 +291,7 @@ void orc_hessian(int nx, int ny, int nz, const double *psi, double *hess)
 void orc_laplacian(int nx, int ny, int nz, const double *psi, double *lap)
 {
     lattice_init();
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++)
@@ -318,7 +323,7 @@ void orc_curvature(int nx, int ny, int nz, const double *phi, double *K, double 
 {
     lattice_init();
     long N = (long)nx * ny * nz;
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -385,7 +390,7 @@ void orc_ac_update(int nx, int ny, int nz, const double *phi, const double *u, d
     double kappa = 4.0 * D / width;
     double *Qv = (double *)malloc(sizeof(double) * 3 * N); /* phi (1 - phi) n at every site */
     double *J = (double *)malloc(sizeof(double) * 3 * N);  /* flux through the face x + e_a / 2 */
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -400,7 +405,7 @@ void orc_ac_update(int nx, int ny, int nz, const double *phi, const double *u, d
                     J[a * N + s] = face_flux(nx, ny, nz, phi, u, x, y, z, a);
                 }
             }
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -465,7 +470,7 @@ void orc_forcing_window(const double *modes, int n_modes, int nx, int ny, int nz
 {
     const long W = (long)wx * wy * wz;
     memset(out, 0, sizeof(double) * 3 * W);
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)wx * wy * wz))
     for (long k = 0; k < wz; k++)
         for (long j = 0; j < wy; j++)
             for (long i = 0; i < wx; i++) {
@@ -547,7 +552,7 @@ static void mlp_one(const double *w, const double *xin, double h1[H1], double h2
 
 void orc_mlp_forward(const double *w, const double *x, long B, double *y)
 {
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par(B * 64))
     for (long b = 0; b < B; b++) {
         double h1[H1], h2[H2];
         mlp_one(w, x + NIN * b, h1, h2, y + NOUT * b);
@@ -772,7 +777,7 @@ orc_state *orc_create(const orc_params *p, const double *phi0, const double *u0,
     /* f^0 = f^eq(p*0, u0) + w H : A0 / (2 c_s^4), A0 = -c_s^2 tau (grad u0 + grad u0^T),
      * the second-order coefficient of Sec. 2.2 with the lattice gradient */
     int nx = p->nx, ny = p->ny, nz = p->nz;
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
@@ -823,7 +828,7 @@ void orc_step(orc_state *s, long nsteps)
     long N = s->N;
     for (long it = 0; it < nsteps; it++) {
         /* 1. collide every site with the fields of time n */
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
         for (long z = 0; z < nz; z++)
             for (long y = 0; y < ny; y++)
                 for (long x = 0; x < nx; x++) {
@@ -860,7 +865,7 @@ void orc_step(orc_state *s, long nsteps)
             }
         }
         /* 3. streaming: f_i(x, n+1) = f^post_i(x - c_i, n) */
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
         for (long z = 0; z < nz; z++)
             for (long y = 0; y < ny; y++)
                 for (long x = 0; x < nx; x++) {
@@ -886,7 +891,7 @@ void orc_moments(const orc_state *s, double *rho, double *pr, double *u, double 
     const orc_params *p = &s->p;
     int nx = p->nx, ny = p->ny, nz = p->nz;
     long N = s->N;
-#pragma omp parallel for
+#pragma omp parallel for if (orc_par((long)nx * ny * nz))
     for (long z = 0; z < nz; z++)
         for (long y = 0; y < ny; y++)
             for (long x = 0; x < nx; x++) {
