@@ -573,7 +573,7 @@ BatchOffsets batch_offsets(int n)
     o.first = off;
     off = align_up(off + sizeof(uint32_t) * ((size_t)n + 1));
     o.counter = off;
-    off = align_up(off + sizeof(uint32_t) * 4 * 2);  // one pair of queue counters per kernel kind
+    off = align_up(off + sizeof(uint32_t) * 4 * lbm::QCOUNTERS);  // queue counters of the four kernel kinds
     o.total = off;
     return o;
 }
@@ -618,8 +618,8 @@ int batch_upload(lbm_batch *b)
         }
         first[i + 1] = first[i] + (uint32_t)b->P[i].nblocks;
     }
-    // all queue counters start at zero (each launch clears the other one of its pair)
-    hipError_t e = hipMemsetAsync(b->d_counter(), 0, 4 * 2 * sizeof(uint32_t), b->stream);
+    // all queue counters start at zero (each launch clears the other parity's counters)
+    hipError_t e = hipMemsetAsync(b->d_counter(), 0, 4 * lbm::QCOUNTERS * sizeof(uint32_t), b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_tab(), b->P.data(), sizeof(lbm::Params) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -643,18 +643,20 @@ hipError_t batch_launch(lbm_batch *b, int parity, hipStream_t s)
 {
     const int n = (int)b->m.size();
     if (b->ml) {
-        hipError_t e = lbm::launch_mlp_pass_batch(b->d_tab(), b->d_buf(3, parity), b->d_first(), n, b->d_counter() + 6,
-                                                  parity, b->fix, b->tile, b->grid_ml, s);
+        hipError_t e = lbm::launch_mlp_pass_batch(b->d_tab(), b->d_buf(3, parity), b->d_first(), n,
+                                                  b->d_counter() + 3 * lbm::QCOUNTERS, parity, b->fix, b->tile,
+                                                  b->grid_ml, s);
         if (e != hipSuccess) return e;
     }
     hipError_t e = lbm::launch_step_batch(b->d_tab(), b->d_buf(0, parity), b->d_first(), n, b->d_counter(), parity,
                                           b->storage, b->tp, b->frc, b->ml, b->fix, b->phys, b->tile, b->grid, s);
     if (e == hipSuccess && b->rk3)
-        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(1, parity), b->d_first(), n, b->d_counter() + 2, parity,
-                                       0.75, 0.25, b->tile, b->grid_ac, s);
+        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(1, parity), b->d_first(), n,
+                                       b->d_counter() + 1 * lbm::QCOUNTERS, parity, 0.75, 0.25, b->tile, b->grid_ac, s);
     if (e == hipSuccess && b->rk3)
-        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(2, parity), b->d_first(), n, b->d_counter() + 4, parity,
-                                       1.0 / 3.0, 2.0 / 3.0, b->tile, b->grid_ac, s);
+        e = lbm::launch_ac_stage_batch(b->d_tab(), b->d_buf(2, parity), b->d_first(), n,
+                                       b->d_counter() + 2 * lbm::QCOUNTERS, parity, 1.0 / 3.0, 2.0 / 3.0, b->tile,
+                                       b->grid_ac, s);
     return e;
 }
 

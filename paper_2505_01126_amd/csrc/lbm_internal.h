@@ -15,6 +15,7 @@ constexpr int NTHREADS = TX * TY;
 constexpr int MAX_MODES = 64;
 constexpr int NRED = 10;
 constexpr int RED_BLOCKS = 1024;  // fixed grid of the reduction (deterministic order)
+constexpr int QCOUNTERS = 2;  // work-queue counters of one kernel kind (one per launch parity)
 
 // Body-force tables, built on the host in FP64 from the mode table (|kx| <= 2)
 // and stored as FP32:

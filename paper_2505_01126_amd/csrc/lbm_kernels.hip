@@ -125,7 +125,7 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     if (valid) {
         float aext[3] = {0.f, 0.f, 0.f};
         if constexpr (FRC) {
-            forcing_at(P, P.fx[x], (uint32_t)z * ny + y, aext);
+            forcing_at<false>(P, P.fx[x], (uint32_t)z * ny + y, aext);
         }
         site_macro<TP>(M, G, fs, aext, P, m);
     }
@@ -156,6 +156,58 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(Params P, const void *fin,
         u[2 * (size_t)N + s] = m.u[2];
     }
     if (phi_out) phi_out[s] = TP ? phi_load(phi, s, P.phi_fix) : 0.0;
+}
+
+// Wavefront reductions in FP64: a butterfly over the 64 lanes (xor
+// partners 32, 16, .., 1).  Each lane combines the same two operands in the same
+// order as its partner, so all lanes end with the same bits, and the pattern is
+// fixed, so the result does not depend on scheduling.
+constexpr bool red_is_max(int k) { return k == 7 || k == 8; }
+template <int K> __device__ __forceinline__ double wave_reduce(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = red_is_max(K) ? fmax(v, w) : v + w;
+    }
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// the NRED statistics of this workgroup: one wavefront reduction per
+// statistic, then lane 0 of every wave writes its value and thread k < NRED
+// combines the NTHREADS / 64 wave values of statistic k in a fixed order
+__device__ __forceinline__ void block_reduce(const double (&acc)[NRED], double (&wred)[NTHREADS / 64][NRED],
+                                            double &res)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[NRED];
+    v[0] = wave_reduce<0>(acc[0]);
+    v[1] = wave_reduce<1>(acc[1]);
+    v[2] = wave_reduce<2>(acc[2]);
+    v[3] = wave_reduce<3>(acc[3]);
+    v[4] = wave_reduce<4>(acc[4]);
+    v[5] = wave_reduce<5>(acc[5]);
+    v[6] = wave_reduce<6>(acc[6]);
+    v[7] = wave_reduce<7>(acc[7]);
+    v[8] = wave_reduce<8>(acc[8]);
+    v[9] = wave_reduce<9>(acc[9]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NRED; k++) wred[wave][k] = v[k];
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < NRED) {
+        res = wred[0][k];
+#pragma unroll
+        for (int w = 1; w < NTHREADS / 64; w++) res = red_is_max(k) ? fmax(res, wred[w][k]) : res + wred[w][k];
+    }
 }
 
 // FP64 partial sums per block over a fixed grid-stride partition, combined in
@@ -204,27 +256,16 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce(Params P, const void *fin, 
         acc[7] = fmax(acc[7], sqrt(u2));
         acc[8] = TP ? fmax(acc[8], fmax(ph - 1.0, fmax(-ph, 0.0))) : 0.0;
     }
-    __shared__ double red[NRED][NTHREADS];
-#pragma unroll
-    for (int k = 0; k < NRED; k++) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = NTHREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int k = 0; k < NRED; k++) {
-                const double o = red[k][threadIdx.x + w];
-                red[k][threadIdx.x] = (k == 7 || k == 8) ? fmax(red[k][threadIdx.x], o) : red[k][threadIdx.x] + o;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < NRED) partials[(size_t)blockIdx.x * NRED + threadIdx.x] = red[threadIdx.x][0];
+    __shared__ double wred[NTHREADS / 64][NRED];
+    double res = 0.0;
+    block_reduce(acc, wred, res);
+    if (threadIdx.x < NRED) partials[(size_t)blockIdx.x * NRED + threadIdx.x] = res;
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partials, int nblocks, int fix, double *out)
 {
-    __shared__ double red[NRED][NTHREADS];
-    __shared__ long long redq[NTHREADS];
+    __shared__ double wred[NTHREADS / 64][NRED];
+    __shared__ long long wq[NTHREADS / 64];
     double acc[NRED];
     long long q = 0;  // fixed-point phi: integer sum of q
 #pragma unroll
@@ -233,27 +274,20 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_final(const double *partial
 #pragma unroll
         for (int k = 0; k < NRED; k++) {
             const double v = partials[(size_t)b * NRED + k];
-            acc[k] = (k == 7 || k == 8) ? fmax(acc[k], v) : acc[k] + v;
+            acc[k] = red_is_max(k) ? fmax(acc[k], v) : acc[k] + v;
         }
         if (fix) q += (long long)partials[(size_t)b * NRED];
     }
+    q = wave_sum_i64(q);
+    if ((threadIdx.x & 63) == 0) wq[threadIdx.x >> 6] = q;
+    double res = 0.0;
+    block_reduce(acc, wred, res);  // its barrier also publishes wq
+    if (threadIdx.x < NRED) {
+        long long qs = 0;
 #pragma unroll
-    for (int k = 0; k < NRED; k++) red[k][threadIdx.x] = acc[k];
-    redq[threadIdx.x] = q;
-    __syncthreads();
-    for (int w = NTHREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int k = 0; k < NRED; k++) {
-                const double o = red[k][threadIdx.x + w];
-                red[k][threadIdx.x] = (k == 7 || k == 8) ? fmax(red[k][threadIdx.x], o) : red[k][threadIdx.x] + o;
-            }
-            redq[threadIdx.x] += redq[threadIdx.x + w];
-        }
-        __syncthreads();
+        for (int w = 0; w < NTHREADS / 64; w++) qs += wq[w];
+        out[threadIdx.x] = (fix && threadIdx.x == 0) ? (double)qs * 0x1p-30 : res;
     }
-    if (threadIdx.x < NRED)
-        out[threadIdx.x] = (fix && threadIdx.x == 0) ? (double)redq[0] * 0x1p-30 : red[threadIdx.x][0];
 }
 
 // --------------------------------------------------------------- launchers

@@ -63,12 +63,13 @@ template <> struct Pop<1> {
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v)  // round to nearest even
     {
-        // the FP32 value is materialised first: otherwise the compiler may fuse
-        // the multiply-add that produced it into the conversion (one rounding
-        // instead of two) in some template variants and not in others, and
-        // the variants would no longer agree bit for bit
-        asm("" : "+v"(v));
-        return (T)v;
+        // the conversion is an instruction of its own: the compiler could
+        // otherwise fuse the multiply-add that produced v into it (one
+        // rounding instead of two) in some template variants and not in
+        // others, and the variants would no longer agree bit for bit
+        uint32_t r;
+        asm("v_cvt_f16_f32 %0, %1" : "=v"(r) : "v"(v));
+        return __builtin_bit_cast(T, (uint16_t)r);
     }
 };
 template <> struct Pop<2> {
@@ -76,12 +77,11 @@ template <> struct Pop<2> {
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v)  // round to nearest even
     {
-        // the FP32 value is materialised first: otherwise the compiler may fuse
-        // the multiply-add that produced it into the conversion (one rounding
-        // instead of two) in some template variants and not in others, and
-        // the variants would no longer agree bit for bit
-        asm("" : "+v"(v));
-        return (T)v;
+        // an instruction of its own, as for FP16 (the low half of the packed
+        // conversion of (v, 0))
+        uint32_t r;
+        asm("v_cvt_pk_bf16_f32 %0, %1, 0" : "=v"(r) : "v"(v));
+        return __builtin_bit_cast(T, (uint16_t)r);
     }
 };
 
@@ -548,12 +548,28 @@ __device__ __forceinline__ void q_of(const float (&v)[27], float (&q)[3])
 // field).  The host groups the modes by |kx| and folds the y and z phases into
 // per-row coefficients (see lbm_internal.h); a site combines its row's 15
 // coefficients with the x twiddles ex = (cos t, sin t, cos 2t, sin 2t).
+// UNIFORM: the row is the same in every lane of the wave (one x-row per wave);
+// its coefficients are then read with scalar loads through the constant
+// address space (the table is read-only while a step runs), which the scalar
+// data cache serves and which leave the vector-memory counter to the
+// population loads.
+#define LBM_CONST __attribute__((address_space(4)))
+template <bool UNIFORM>
 __device__ __forceinline__ void forcing_at(const Params &P, float4 ex, uint32_t row, float (&a)[3])
 {
-    const LBM_GLOBAL float *r = gconst(P.frow) + (size_t)row * FROW;
+    float c[15];
+    if constexpr (UNIFORM) {
+        const LBM_CONST float *r = (const LBM_CONST float *)P.frow + (size_t)row * FROW;
+#pragma unroll
+        for (int k = 0; k < 15; k++) c[k] = r[k];
+    } else {
+        const LBM_GLOBAL float *r = gconst(P.frow) + (size_t)row * FROW;
+#pragma unroll
+        for (int k = 0; k < 15; k++) c[k] = r[k];
+    }
 #pragma unroll
     for (int d = 0; d < 3; d++)
-        a[d] = r[d] + (r[3 + d] * ex.x + r[6 + d] * ex.y) + (r[9 + d] * ex.z + r[12 + d] * ex.w);
+        a[d] = c[d] + (c[3 + d] * ex.x + c[6 + d] * ex.y) + (c[9 + d] * ex.z + c[12 + d] * ex.w);
 }
 
 // ------------------------------------------------------------ fused step
@@ -639,8 +655,12 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     const int bz = (int)(L / ((uint32_t)P.gx * (uint32_t)P.gy));
     const int x0 = bx * TXW, y0 = by * TYW, z0 = bz * P.zchunk;
     const int zend = min(z0 + P.zchunk, nz);
+    // Lanes past the box's edge (a ragged last tile) step the periodic image of
+    // their site: the same inputs give the same bits, so their writes repeat
+    // the owner's.  Keeping every lane busy keeps every memory operation
+    // unconditional, so the compiler counts the loads in flight exactly instead
+    // of draining all of them (stores included) before the next plane.
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
-    const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     // every tile row of populations, u and phi fills whole 128-byte lines
     const bool nt_rows = (TW * ES) % 128 == 0 && nx % 64 == 0;
     const T *__restrict__ fin = (const T *)B.fin;
@@ -839,18 +859,24 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             jz_left = face_flux(v[0], v[1], v[2], v[3], v[4], v[5], um, uz_c);
         }
     }
-    if (LBM && active) fetch_pops(z0);
+    if (LBM) fetch_pops(z0);
 
     for (int z = z0; z < zend; z++) {
         const bool more = z + 1 < zend;
+        // The prefetches for the next plane run in the last plane of the chunk
+        // too, re-reading the current plane's data (in L2, valid addresses): an
+        // unconditional load keeps the prefetched values in the same registers
+        // on every path, where a skipped one made the compiler copy all 27
+        // populations and the other prefetched values on both sides of the branch.
+        const int zn = more ? z + 1 : z;
         if constexpr (TP) {
             store_plane(z + 3);
-            if (more) fetch_plane(z + 4);
+            fetch_plane(zn + 3);
             lds_barrier();
             if constexpr (!PRE) {
                 compute_q(z + 1);
                 compute_faces(z);
-                if (more) fetch_face_u(z + 1);
+                fetch_face_u(zn);
             }
             lds_barrier();
         }
@@ -867,7 +893,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             const float *pc = sphi[ring(z)];
             const float *pp = sphi[ring(z + 1)];
             const float c0 = pc[lc];
-            const bool cand = active && c0 > 0.02f && c0 < 0.98f;
+            const bool cand = c0 > 0.02f && c0 < 0.98f;
             float y[4] = {0.f, 0.f, 0.f, 0.f};
             if (__ballot(cand) != 0ull) {
                 if (cand) {
@@ -891,7 +917,9 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             }
             continue;
         }
-        if (active) {
+        float aext[3] = {0.f, 0.f, 0.f};
+        float y[4] = {0.f, 0.f, 0.f, 0.f};  // learned curvature: network output at a selected cell
+        {
             if constexpr (LBM) {
                 float hf[27];
 #pragma unroll
@@ -901,7 +929,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                 }
                 moments10(hf, M);
             }
-            if (LBM && !kLatePrefetch && more) fetch_pops(z + 1);
+            if (LBM && !kLatePrefetch) fetch_pops(zn);
 
             if constexpr (TP) {
                 // Allen-Cahn: phi^{n+1} = phi^n - sum (outgoing - incoming) face and link fluxes
@@ -917,7 +945,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     acc[1] = PS::flux(jz_left) - PS::flux(jr);
                     jz_left = jr;
                     uz_c = uz_n;
-                    if (more) uz_n = uz_in[(uint32_t)wrapi(z + 2, nz) * plane + own_xy];
+                    uz_n = uz_in[(uint32_t)wrapi(zn + 1, nz) * plane + own_xy];
                 }
                 {
                     // phase-field stencil of this site (LDS)
@@ -957,31 +985,36 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                                          rk_b * (po + ((acc[0] + acc[1]) + (acc[2] + acc[3])));
                 else
                     gstore(&phout[(size_t)own], PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3])), nt_rows);
-                if (more) po = phin[(size_t)own + plane];
+                po = phin[(size_t)zn * plane + own_xy];
             }
-            if (LBM && kLatePrefetch && more) fetch_pops(z + 1);
+            // Every other load of this plane is issued before the populations of
+            // the next one: loads complete in order, so waiting for a load
+            // issued after the 27 prefetches would wait for them as well.
+            if constexpr (FRC && LBM) forcing_at<TW == 64>(P, ex, (uint32_t)z * ny + yrow, aext);
+            if constexpr (ML) {
+                if (sel) {  // the network output that the learned-curvature pass left here
+                    const LBM_GLOBAL float *yi = gconst((const float *)B.mlpy) + 4 * (size_t)own;
+                    y[0] = yi[0];
+                    y[1] = yi[1];
+                    y[2] = yi[2];
+                    y[3] = yi[3];
+                }
+            }
+            if (LBM && kLatePrefetch) fetch_pops(zn);
         }
         if constexpr (ACO) continue;
         // surface tension: finite differences, or blended with the network
         // output that the learned-curvature pass left for the selected cells
         float fs[3] = {0.f, 0.f, 0.f};
         if constexpr (ML) {
-            if (active) {
-                if (sel) {
-                    const LBM_GLOBAL float *yi = gconst((const float *)B.mlpy) + 4 * (size_t)own;
-                    const float y[4] = {yi[0], yi[1], yi[2], yi[3]};
-                    surface_blend(G, P, kfd, gn, y, fs);
-                } else {
-                    surface_fd(G, P, fs);
-                }
-            }
+            if (sel)
+                surface_blend(G, P, kfd, gn, y, fs);
+            else
+                surface_fd(G, P, fs);
         } else if constexpr (TP) {
-            if (active) surface_fd(G, P, fs);
+            surface_fd(G, P, fs);
         }
-        if (active) {
-            float aext[3] = {0.f, 0.f, 0.f};
-            if constexpr (FRC) forcing_at(P, ex, (uint32_t)z * ny + yrow, aext);
-
+        {
             // moments -> forces, velocity
             Macro m;
             site_macro<TP, PH>(M, G, fs, aext, P, m);
@@ -1013,74 +1046,21 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     }
 }
 
-// The step of one or many independent boxes in one launch (a single box is a
-// batch of one): a persistent grid takes work items (box, tile) from a queue,
-// so the load stays balanced to the last item; item k belongs to the box b with
-// first[b] <= k < first[b + 1].  The queue counter of this launch is
-// counter[parity]; the launch clears the other one for the next launch on the
-// stream.  tab[b] and buf[b] are the box's parameters and this step's buffers.
-// One Runge-Kutta stage of the phase field of one or many boxes, the same
-// persistent queue over the same work items (buf[b].phin: the stage input,
-// buf[b].phin0: phi^n, buf[b].phout: the stage output).
-template <int TW>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
-k_ac_stage_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
-                 int nbox, uint32_t *counter, int parity, double rk_a, double rk_b)
-{
-    __shared__ uint32_t s_item;
-    const int tid = threadIdx.y * TW + threadIdx.x;
-    const uint32_t total = first[nbox];
-    if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(&counter[parity], 1u);
-        __syncthreads();
-        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (item >= total) break;
-        int lo = 0, hi = nbox - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (first[mid] <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<0, true, false, false, TW, true, false, true>(tab[b], buf[b], item - first[b], rk_a, rk_b);
-    }
-}
-
-// The learned-curvature pass of one or many boxes ahead of their step, on the
-// same persistent queue and work items (buf[b].phin: phi^n; buf[b].mlpy: the
-// network outputs the step reads).
-template <int TW, bool FX>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
-k_mlp_pass_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
-                 int nbox, uint32_t *counter, int parity)
-{
-    __shared__ uint32_t s_item;
-    const int tid = threadIdx.y * TW + threadIdx.x;
-    const uint32_t total = first[nbox];
-    if (blockIdx.x == 0 && tid == 0) counter[parity ^ 1] = 0u;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(&counter[parity], 1u);
-        __syncthreads();
-        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (item >= total) break;
-        int lo = 0, hi = nbox - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (first[mid] <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<0, true, false, true, TW, true, FX, false, false, true>(tab[b], buf[b], item - first[b]);
-    }
-}
-
-template <int S, bool TP, bool FRC, bool ML, int TW, bool FX, bool PH>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
-k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
-             int nbox, uint32_t *counter, int parity)
+// ------------------------------------------------------------ work queue
+// The persistent loop of a batched launch over the boxes of a batch: a
+// workgroup takes the next work item from one queue counter per launch, so the
+// load stays balanced to the last item; item k belongs to the box b with
+// first[b] <= k < first[b + 1].  The counter of this launch is counter[parity];
+// the launch clears the other one for the next launch on the stream.
+// body(b, item within the box) runs with every thread of the workgroup.
+// (Per-die queues, each die draining a contiguous range of items first so that
+// neighbouring tiles share its L2, cut the L2-miss reads by a fifth (FP32) to a
+// third (FP16) but made the FP32 step 2.5 % slower and left FP16 unchanged: the
+// step is not bound by the L2-miss traffic, and one queue keeps all dies on the
+// same z range.)
+template <int TW, class Body>
+__device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ first, int nbox, uint32_t *counter,
+                                           int parity, Body body)
 {
     __shared__ uint32_t s_item;
     const int tid = threadIdx.y * TW + threadIdx.x;
@@ -1099,8 +1079,47 @@ k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, co
             else hi = mid - 1;
         }
         const int b = __builtin_amdgcn_readfirstlane(lo);
-        step_tile<S, TP, FRC, ML, TW, true, FX, false, PH>(tab[b], buf[b], item - first[b]);
+        body(b, item - first[b]);
     }
+}
+
+// One Runge-Kutta stage of the phase field of one or many boxes, on the same
+// work items as the step (buf[b].phin: the stage input, buf[b].phin0: phi^n,
+// buf[b].phout: the stage output).
+template <int TW>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_ac_stage_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+                 int nbox, uint32_t *counter, int parity, double rk_a, double rk_b)
+{
+    batch_loop<TW>(first, nbox, counter, parity, [&](int b, uint32_t L) {
+        step_tile<0, true, false, false, TW, true, false, true>(tab[b], buf[b], L, rk_a, rk_b);
+    });
+}
+
+// The learned-curvature pass of one or many boxes ahead of their step, on the
+// same work items (buf[b].phin: phi^n; buf[b].mlpy: the network outputs the
+// step reads).
+template <int TW, bool FX>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_mlp_pass_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+                 int nbox, uint32_t *counter, int parity)
+{
+    batch_loop<TW>(first, nbox, counter, parity, [&](int b, uint32_t L) {
+        step_tile<0, true, false, true, TW, true, FX, false, false, true>(tab[b], buf[b], L);
+    });
+}
+
+// The time step of one or many independent boxes in one launch (a single box
+// is a batch of one); tab[b] and buf[b] are the box's parameters and this
+// step's buffers.
+template <int S, bool TP, bool FRC, bool ML, int TW, bool FX, bool PH>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_step_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
+             int nbox, uint32_t *counter, int parity)
+{
+    batch_loop<TW>(first, nbox, counter, parity, [&](int b, uint32_t L) {
+        step_tile<S, TP, FRC, ML, TW, true, FX, false, PH>(tab[b], buf[b], L);
+    });
 }
 
 // ------------------------------------------------------- step dispatch
