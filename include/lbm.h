@@ -17,7 +17,8 @@
  *   Vector fields are component major (SoA): v[c * N + s], c = x, y, z.
  *   Lattice units: dx = dt = 1, c_s^2 = 1/3, nu = c_s^2 (tau - 1/2).
  *   All device pointers belong to the caller; the library never allocates or
- *   frees device memory.  Every call is asynchronous on the stream given to
+ *   frees device memory (it owns one fixed device array, the scratch of
+ *   lbm_mlp_backward_static).  Every call is asynchronous on the stream given to
  *   lbm_init / lbm_set_stream unless stated otherwise.
  *   One handle per stream; a handle is not thread safe.
  *
@@ -36,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 4
+#define LBM_ABI_VERSION 5
 #define LBM_NRED 10          /* number of lbm_reduce outputs */
 #define LBM_MAX_MODES 64     /* forcing table rows */
 #define LBM_MLP_NPARAM 6212  /* 27*64+64 + 64*64+64 + 64*4+4 */
@@ -46,7 +47,8 @@ enum {
     LBM_EINVAL = -1,   /* bad dimensions or parameters */
     LBM_ENOSPACE = -2, /* workspace smaller than lbm_workspace_bytes() */
     LBM_EHIP = -3,     /* a HIP runtime error (text in lbm_last_error) */
-    LBM_ESTATE = -4    /* call not valid in the handle's state */
+    LBM_ESTATE = -4,   /* call not valid in the handle's state */
+    LBM_ERANGE = -5    /* a size above the fixed maximum of an entry point without a workspace */
 };
 
 /* population storage: FP32, or FP16 / BF16 holding h_i = f_i / w_i - P0
@@ -184,6 +186,22 @@ int lbm_mlp_forward(const uint16_t *d_w, const uint16_t *d_x, int64_t batch, flo
  * bytes of device scratch.  Deterministic (fixed reduction order). */
 int lbm_mlp_backward(const uint16_t *d_w, const uint16_t *d_x, const float *d_t, int64_t batch, float *d_grad,
                      float *d_loss, void *d_work, size_t work_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * gradient and loss as lbm_mlp_backward, bit for bit, with the block partials
+ * in a device array that the library owns instead of a caller workspace.  The
+ * array holds the partials of up to LBM_MLP_STATIC_MAX_BATCH samples (256
+ * blocks x 6213 floats = 6.4 MB), one copy on each GPU the library runs on,
+ * kept until the process ends.  batch > LBM_MLP_STATIC_MAX_BATCH returns
+ * LBM_ERANGE; NULL pointers or batch < 0 return LBM_EINVAL.  No device memory
+ * is allocated or freed.  Each call overwrites every partial it reads, so
+ * nothing has to be cleared between calls, but all calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and give wrong results.  Asynchronous on stream. */
+#define LBM_MLP_STATIC_MAX_BATCH 16384
+int lbm_mlp_backward_static(const uint16_t *d_w, const uint16_t *d_x, const float *d_t, int64_t batch,
+                            float *d_grad, float *d_loss, void *stream);
 
 /* One Adam step on FP32 master weights (Kingma & Ba): m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, w -= lr mhat / (sqrt(vhat) + eps) with bias correction

@@ -542,6 +542,7 @@ const char *lbm_strerror(int code)
     case LBM_ENOSPACE: return "workspace too small";
     case LBM_EHIP: return "HIP runtime error";
     case LBM_ESTATE: return "invalid state";
+    case LBM_ERANGE: return "size above the fixed maximum of an entry point without a workspace";
     default: return "unknown error";
     }
 }

@@ -9,6 +9,9 @@
 //   C: column l % 16, rows 4 (l / 16) + i, i = 0..3
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+#include "lbm.h"
 #include "lbm_internal.h"
 #include "lbm_mlp_device.h"
 
@@ -387,4 +390,47 @@ hipError_t launch_harvest_write(const Params &p, const void *phi, uint32_t chunk
     return hipGetLastError();
 }
 
+// ------------------------------------------- backward without a workspace
+// The block partials of lbm_mlp_backward_static live in a file-scope device
+// array sized for LBM_MLP_STATIC_MAX_BATCH samples, one instance per GPU for
+// the life of the process.  On the host the array's name is only a stand-in
+// for the symbol: kernels get the device address that hipGetSymbolAddress
+// returns, looked up once per device (the first call on that device).
+constexpr int STATIC_BLOCKS = (LBM_MLP_STATIC_MAX_BATCH + CHUNK - 1) / CHUNK;
+static_assert(STATIC_BLOCKS <= 512, "the backward grid is capped at 512 blocks");
+static __device__ __align__(256) float scratch[(size_t)STATIC_BLOCKS * (NPARAM + 1)];
+constexpr int MAX_DEVICES = 64;
+
+hipError_t mlp_static_scratch(float **out)
+{
+    static std::mutex mu;
+    static float *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (float *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 }  // namespace lbm
+
+int lbm_mlp_backward_static(const uint16_t *d_w, const uint16_t *d_x, const float *d_t, int64_t batch, float *d_grad,
+                            float *d_loss, void *stream)
+{
+    if (!d_w || batch < 0 || !d_grad || !d_loss || (batch > 0 && (!d_x || !d_t))) return LBM_EINVAL;
+    if (batch > LBM_MLP_STATIC_MAX_BATCH) return LBM_ERANGE;
+    float *partial = nullptr;
+    if (lbm::mlp_static_scratch(&partial) != hipSuccess) return LBM_EHIP;
+    return lbm::launch_mlp_backward(d_w, d_x, d_t, batch, d_grad, d_loss, partial, (hipStream_t)stream) ==
+                   hipSuccess
+               ? LBM_OK
+               : LBM_EHIP;
+}

@@ -14,13 +14,14 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(PKG, "liblbm.so")
 
-LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_ESTATE = 0, -1, -2, -3, -4
+LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_ESTATE, LBM_ERANGE = 0, -1, -2, -3, -4, -5
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CURV = {"fd": 0, "mlp": 1}
 PHI_STORAGE = {"f64": 0, "fix32": 1}
 NRED = 10
 MAX_MODES = 64
 MLP_NPARAM = 6212
+MLP_STATIC_MAX_BATCH = 16384  # lbm_mlp_backward_static
 REDUCE_NAMES = ("sum_phi", "sum_rho", "sum_pstar", "sum_rho_ux", "sum_rho_uy", "sum_rho_uz", "kinetic",
                 "max_u", "phi_overshoot", "nonfinite")
 
@@ -62,6 +63,8 @@ SYMBOLS = {
     "lbm_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "lbm_mlp_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lbm_mlp_backward_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
     "lbm_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
                                C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "lbm_set_mlp": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -168,6 +171,11 @@ def lbm_mlp_forward(d_w, d_x, batch, d_y, stream):
 def lbm_mlp_backward(d_w, d_x, d_t, batch, d_grad, d_loss, d_work, work_bytes, stream):
     _check(load_library().lbm_mlp_backward(d_w, d_x, d_t, int(batch), d_grad, d_loss, d_work, work_bytes, stream),
            None, "lbm_mlp_backward")
+
+
+def lbm_mlp_backward_static(d_w, d_x, d_t, batch, d_grad, d_loss, stream):
+    _check(load_library().lbm_mlp_backward_static(d_w, d_x, d_t, int(batch), d_grad, d_loss, stream), None,
+           "lbm_mlp_backward_static")
 
 
 def lbm_mlp_adam(d_master, d_m, d_v, d_grad, d_w16, step, lr, beta1, beta2, eps, stream):
