@@ -17,9 +17,14 @@ Bars on the relative L2 error of u: 1e-5 (FP32), 1e-3 (FP16), 1e-2 (BF16,
 8-bit mantissa); phi within 1e-5 (FP32) or 1e-3 (16-bit storage: 500 steps of
 advection by a velocity that differs by ~1e-4 relative); sum phi equal to the
 oracle's within 1e-12 relative.  The static droplet's velocity is its
-spurious current (~1e-5, from rounding-level force imbalances), on which a
-relative bar measures rounding rather than the method; its bar is on the
-velocity error against the capillary velocity sigma / (rho_l nu) instead.
+spurious current (max 6e-5), the residual of the surface-tension and pressure
+forces, which nearly cancel at every interface cell: FP32 arithmetic leaves
+each term with ~6e-8 relative error, hence ~1e-4 on the residual (the
+GPU-oracle difference of u stays at 4-6e-9 absolute while u decays to the
+spurious level; FP32 storage rounding alone, emulated in the FP64 oracle by
+oracle/droplet_floor.py, moves u by 2.2e-6).  Its bar is on the velocity
+error against the capillary velocity sigma / (rho_l nu) instead; the relative
+errors are printed.
 Each oracle run is shared by the storage modes of its case.
 """
 import math
