@@ -29,7 +29,7 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t f[2], phi[2], u[2], stage[2], mlpy, frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
+    size_t f[2], phi[2], u[2], stage[2], mlpy, iflag, frow, fx, self_batch, partials, red, mlp, sph, hcount, total;
 };
 
 Layout layout_of(const lbm_config &c)
@@ -53,10 +53,11 @@ Layout layout_of(const lbm_config &c)
     } else {
         L.phi[0] = L.phi[1] = L.u[0] = L.u[1] = (size_t)-1;
     }
-    if (c.two_phase && c.curv_mode == LBM_CURV_MLP) {  // network outputs at the interface cells
+    if (c.two_phase && c.curv_mode == LBM_CURV_MLP) {  // network outputs and interface flags
         L.mlpy = take(16 * N);
+        L.iflag = take((size_t)lbm::flag_segments(c.nx) * c.ny * c.nz);
     } else {
-        L.mlpy = (size_t)-1;
+        L.mlpy = L.iflag = (size_t)-1;
     }
     if (c.two_phase && c.ac_rk3) {  // the two intermediate Runge-Kutta stages of phi
         L.stage[0] = take(8 * N);
@@ -190,6 +191,7 @@ struct lbm_handle {
     void *phi(int k) { return cfg.two_phase ? (void *)(ws + L.phi[k]) : nullptr; }
     void *stage(int k) { return cfg.two_phase && cfg.ac_rk3 ? (void *)(ws + L.stage[k]) : nullptr; }
     void *mlpy() { return cfg.two_phase && cfg.curv_mode == LBM_CURV_MLP ? (void *)(ws + L.mlpy) : nullptr; }
+    uint8_t *iflag() { return cfg.two_phase && cfg.curv_mode == LBM_CURV_MLP ? (uint8_t *)(ws + L.iflag) : nullptr; }
     float *u(int k) { return cfg.two_phase ? (float *)(ws + L.u[k]) : nullptr; }
 
     int fail(int code, const std::string &msg)
@@ -360,6 +362,8 @@ int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_byte
         P.fx = dx;
     }
     hipError_t e = lbm::launch_init(P, cfg->storage, h->f(0), h->phi(0), h->u(0), d_phi0, d_u0, d_pstar0, h->stream);
+    if (e == hipSuccess && h->iflag())  // every item holds interface cells until a step has flagged them
+        e = hipMemsetAsync(h->iflag(), 1, (size_t)lbm::flag_segments(cfg->nx) * cfg->ny * cfg->nz, h->stream);
     if (e == hipSuccess && P.gravity_on) {
         // box-mean density from sum phi of the initial state (finite-difference
         // curvature for this reduction: the network weights are not set yet)
@@ -605,16 +609,19 @@ int batch_upload(lbm_batch *b)
             const int c = h->cur ^ p, o = c ^ 1;
             // with the Runge-Kutta update the step's own Euler update of phi
             // is the first stage (into stage 0); stages 2 and 3 follow
+            // the kernel that writes a step's final phi also writes the interface
+            // flags that the next network pass reads (with Runge-Kutta, the last stage)
             buf[(size_t)p * n + i] = lbm::Buffers{h->f(c), h->f(o), h->phi(c), b->rk3 ? h->stage(0) : h->phi(o),
-                                                  h->u(c), h->u(o), nullptr, h->mlpy()};
+                                                  h->u(c), h->u(o), nullptr, h->mlpy(),
+                                                  b->rk3 ? nullptr : h->iflag()};
             if (b->ml)
-                buf[(size_t)(6 + p) * n + i] =
-                    lbm::Buffers{nullptr, nullptr, h->phi(c), nullptr, nullptr, nullptr, nullptr, h->mlpy()};
+                buf[(size_t)(6 + p) * n + i] = lbm::Buffers{nullptr, nullptr, h->phi(c), nullptr, nullptr,
+                                                            nullptr, nullptr, h->mlpy(), h->iflag()};
             if (b->rk3) {
                 buf[(size_t)(2 + p) * n + i] =
                     lbm::Buffers{nullptr, nullptr, h->stage(0), h->stage(1), h->u(c), nullptr, h->phi(c)};
-                buf[(size_t)(4 + p) * n + i] =
-                    lbm::Buffers{nullptr, nullptr, h->stage(1), h->phi(o), h->u(c), nullptr, h->phi(c)};
+                buf[(size_t)(4 + p) * n + i] = lbm::Buffers{nullptr, nullptr, h->stage(1), h->phi(o), h->u(c),
+                                                            nullptr, h->phi(c), nullptr, h->iflag()};
             }
         }
         first[i + 1] = first[i] + (uint32_t)b->P[i].nblocks;

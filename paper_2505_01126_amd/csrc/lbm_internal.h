@@ -72,7 +72,14 @@ struct Buffers {
     const void *phin0;  // phi^n for the Runge-Kutta stages of the phase field
     void *mlpy;         // learned curvature: network outputs (float4 per site; NaN at the
                         // interface cells the criterion does not select), from the pass before the step
+    uint8_t *iflag;     // learned curvature: interface flags, one byte per 32-site x-segment of a row,
+                        // iflag[(z * ny + y) * nseg + x / 32] (nseg = ceil(nx / 32)), 1 when a site of the
+                        // segment has 0.02 < phi < 0.98; written by the kernel that writes the final
+                        // phi of a step, read by the network pass of the next; nullptr elsewhere
 };
+
+// x-segments of 32 sites per row of the interface flags
+__host__ __device__ inline int flag_segments(int nx) { return (nx + 31) / 32; }
 
 hipError_t launch_init(const Params &p, int storage, void *fout, void *phi_out, float *u_out, const double *phi0,
                        const double *u0, const double *ps0, hipStream_t s);

@@ -661,6 +661,22 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // unconditional, so the compiler counts the loads in flight exactly instead
     // of draining all of them (stores included) before the next plane.
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
+    if constexpr (PRE) {
+        // the network pass skips a work item none of whose sites is an
+        // interface cell (the step leaves nothing to read there): its flags are
+        // the x-segments of its rows in its planes
+        if (B.iflag) {
+            const int nseg = flag_segments(nx);
+            const int s0 = x0 / 32, ns = min((x0 + TXW + 31) / 32, nseg) - s0;
+            const int nr = min(TYW, ny - y0), np = zend - z0;
+            bool any = false;
+            for (int e = tid; e < ns * nr * np; e += NTHREADS) {
+                const int si = e % ns, r = (e / ns) % nr, k = e / (ns * nr);
+                any |= B.iflag[((size_t)(z0 + k) * ny + (y0 + r)) * nseg + s0 + si] != 0;
+            }
+            if (!__syncthreads_or(any)) return;
+        }
+    }
     // every tile row of populations, u and phi fills whole 128-byte lines
     const bool nt_rows = (TW * ES) % 128 == 0 && nx % 64 == 0;
     const T *__restrict__ fin = (const T *)B.fin;
@@ -980,11 +996,26 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     LB_LINK(21) LB_LINK(22) LB_LINK(23) LB_LINK(24) LB_LINK(25) LB_LINK(26)
 #undef LB_LINK
                 }
+                PT pnew;
                 if constexpr (ACO)
-                    phout[(size_t)own] = rk_a * gconst((const double *)B.phin0)[own] +
-                                         rk_b * (po + ((acc[0] + acc[1]) + (acc[2] + acc[3])));
+                    pnew = rk_a * gconst((const double *)B.phin0)[own] +
+                           rk_b * (po + ((acc[0] + acc[1]) + (acc[2] + acc[3])));
                 else
-                    gstore(&phout[(size_t)own], PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3])), nt_rows);
+                    pnew = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
+                gstore(&phout[(size_t)own], pnew, nt_rows && !ACO);
+                if constexpr (ML || ACO) {
+                    // interface flags of the new phi, as the next network pass
+                    // will see it (its FP32 value): one byte per 32-lane half
+                    // of the wave, each half one 32-site segment of one row
+                    if (B.iflag) {
+                        const float pf = PS::f32(pnew);
+                        const uint64_t m = __ballot(pf > 0.02f && pf < 0.98f);
+                        const int lane = tid & 63;
+                        if ((lane & 31) == 0 && x0 + tx < nx && y0 + ty < ny)
+                            B.iflag[((size_t)z * ny + yg) * flag_segments(nx) + xg / 32] =
+                                (uint8_t)(((lane < 32 ? m : m >> 32) & 0xffffffffull) != 0);
+                    }
+                }
                 po = phin[(size_t)zn * plane + own_xy];
             }
             // Every other load of this plane is issued before the populations of

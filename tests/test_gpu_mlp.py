@@ -192,3 +192,44 @@ def test_step_with_learned_curvature_matches_oracle():
           f"oracle runs by {dfd:.3e}; u bar {bar:.3e}")
     check(m, mo, "f32", "learned-curvature step", u_bar=bar, p_bar=p_bar, phi_bar=1e-5, drho=0.9)
     assert dfd > 1e-3 and n > 100
+
+
+def test_learned_curvature_with_moving_interface_matches_oracle():
+    """A droplet carried through small work items (z-chunks of 4 planes) by a
+    uniform flow: its interface enters items that held none at the previous
+    step, which the network pass must not skip (it skips items whose sites
+    the previous step flagged as free of interface cells)."""
+    import torch
+
+    lbm = _lbm()
+    shape = (40, 20, 24)
+    phi0, c = I.droplet(shape, 4.0, 4.0, center=(11.6, 10.3, 12.8))
+    u0 = np.zeros((3,) + shape)
+    u0[2] = 0.04  # along z: 2.4 cells in 60 steps, across z-chunk boundaries
+    w = _mlp_case_weights(33)
+    kw = dict(rho_l=1.0, rho_g=1.0, sigma=0.005, mobility=0.05, width=4.0, p0=0.0)
+    print("case moving droplet, learned curvature, zchunk 4", flush=True)
+    g = lbm.Lattice(shape, 0.8, phi0=phi0, u0=u0, zchunk=4, curv_mode="mlp", **kw)
+    g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
+    g.step(60)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    X, _, n = g.harvest(np.array([c]), np.array([4.0]), cap=1 << 16)
+    y_gpu = lbm.Mlp(w).forward(X).double().cpu().numpy()
+    g.close()
+    y_orc = O.mlp_forward(w, X.cpu().numpy().view(np.float16)[:, :27].astype(np.float64))
+    e_net = np.linalg.norm(y_gpu - y_orc) / np.linalg.norm(y_orc)
+    e_net_max = np.abs(y_gpu - y_orc).max() / np.abs(y_orc).max()
+    o = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, curv_mode=1, mlp=w, **kw)
+    o.step(60)
+    mo = o.moments()
+    ofd = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, **kw)
+    ofd.step(60)
+    mfd = ofd.moments()
+    dfd = np.linalg.norm(mfd["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    dfd_p = np.abs(mfd["p"] - mo["p"]).max() / np.abs(mo["p"] - mo["p"].mean()).max()
+    zc = [float((mo["phi"] * np.arange(shape[0])[:, None, None]).sum() / mo["phi"].sum())]
+    print(f"moving droplet: centre z {c[2]:.2f} -> {zc[0]:.2f}; network outputs differ by {e_net:.3e} on {n} cells; "
+          f"FD vs learned oracle runs by {dfd:.3e}")
+    check(m, mo, "f32", "moving droplet, learned curvature", u_bar=1e-5 + 2.0 * e_net * dfd,
+          p_bar=1e-5 + 2.0 * e_net_max * dfd_p, phi_bar=1e-5, drho=0.0)
+    assert dfd > 1e-4 and zc[0] - c[2] > 2.0
