@@ -17,8 +17,12 @@ A step is one fused kernel launch over the whole box (three launches with ":rk3"
 HBM before timing starts; W untimed warm-up steps, then R blocks of K timed
 steps, each between two stream synchronisations and timed with HIP events on
 the launch stream; the median block is reported.  The learned-curvature
-variants run the same workload with the network blend switched on (seeded
-weights: the cost does not depend on their values).
+variants run the same workload with the network blend switched on, with the
+network that train_curvature trains (paper_2505_01126_amd/curvature_mlp.npy).
+
+The small-bubble leg times the same recipe with 256 bubbles of d = 4..6 and
+reports Laplace's law on those bubbles at rest (no velocity, no forcing) after
+1000 steps: finite differences against the trained network's blend.
 
 Each variant also reports its error against the FP64 oracle on a 64^3 box of
 the same recipe after 50 steps (relative L2 of u, max |phi| difference).
@@ -82,18 +86,30 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def workload(n, seed=0, diameter=16.0):
-    """The bubbly-HIT recipe on n^3; `diameter` is a number or a (lo, hi)
-    range sampled per bubble (the small-bubble run uses (4, 6))."""
+TWO_PHASE = dict(rho_l=1.0, rho_g=0.1, sigma=0.005, mobility=0.05, width=4.0, p0=0.0)
+WEIGHTS = os.path.join(ROOT, "paper_2505_01126_amd", "curvature_mlp.npy")
+
+
+def bubbles(n, seed=0, diameter=16.0):
+    """The seeded bubble field of the recipe on n^3 (256 bubbles at 512^3, the
+    same number density at other sizes): (shape, phi0, centres, radii, count)."""
     from paper_2505_01126_amd import inputs as I
 
     shape = (n, n, n)
     nb = max(1, int(round(256 * (n / 512.0) ** 3)))
     phi0, centers, radii = I.bubble_pack(shape, nb, diameter, width=4.0, seed=seed)
+    return shape, phi0, centers, radii, nb
+
+
+def workload(n, seed=0, diameter=16.0):
+    """The bubbly-HIT recipe on n^3; `diameter` is a number or a (lo, hi)
+    range sampled per bubble (the small-bubble run uses (4, 6))."""
+    from paper_2505_01126_amd import inputs as I
+
+    shape, phi0, _, _, nb = bubbles(n, seed, diameter)
     u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=seed + 1)
     modes = I.forcing_modes(1e-5, seed=seed + 2)
-    params = dict(rho_l=1.0, rho_g=0.1, sigma=0.005, mobility=0.05, width=4.0, p0=0.0, modes=modes)
-    return shape, phi0, u0, params, nb
+    return shape, phi0, u0, dict(TWO_PHASE, modes=modes), nb
 
 
 def traffic_for(workload_name, storage):
@@ -108,6 +124,17 @@ def traffic_for(workload_name, storage):
     if not rec or rec.get("kernel_sha") != kernel_sha():
         return None
     return rec.get("bytes_per_launch")
+
+
+def trained_weights(path=WEIGHTS):
+    """The network trained by train_curvature (seed 0, its default recipe), as
+    a device tensor of fp16 bits."""
+    import torch
+
+    w = np.load(path, allow_pickle=False)
+    if w.size != 6212:
+        raise SystemExit(f"bench.py: {path} holds {w.size} values, not the network's 6212")
+    return torch.tensor(w.astype(np.float16).view(np.int16).reshape(-1), device="cuda")
 
 
 def mlp_weights(seed=5):
@@ -129,7 +156,7 @@ def time_variant(shape, phi0, u0, params, storage, steps, warmup, repeats, tau, 
     g = lbm.Lattice(shape, tau, phi0=phi0, u0=u0, storage=storage, zchunk=zchunk, curv_mode=curv, phi_storage=phs,
                     ac_rk3=rk3, **params)
     if curv == "mlp":
-        g.set_mlp(torch.tensor(mlp_weights().astype(np.float16).view(np.int16), device="cuda"))
+        g.set_mlp(trained_weights())
     r0 = g.reduce()
     stream = g.stream
     g.step(warmup)
@@ -209,9 +236,75 @@ def batch_leg(steps, warmup, repeats, count=128, seed=3):
             "speedup": ms_single / ms_batch}
 
 
-def small_bubble_leg(steps, warmup, repeats, n=512):
+def bubble_laplace(n=512, seed=0, diameter=(4.0, 6.0), curv="fd", w16=None, k_lo=0.0, k_hi=0.0,
+                   checkpoints=(1000,), window=10):
+    """Laplace's law on the bubbles of the recipe, at rest: no initial
+    velocity and no forcing, FP32 populations, tau = 0.515, density ratio 10.
+    At each checkpoint (steps from the start), per bubble whose nearest
+    neighbour centre is at least 2 window + 2 away: R_eff from the gas volume
+    sum (1 - phi) within `window` of its centre, dp = mean p within 1 of the
+    centre - mean p at 8..10, and e = dp / (2 sigma / R_eff) - 1.  Returns,
+    per checkpoint, the mean and mean |e| over those bubbles, the largest
+    |e|, the R_eff range and the spurious currents: the largest |u| within
+    `window` of the measured bubbles' centres, and max |u_a| over the box
+    (which also sees closer pairs of bubbles)."""
+    import torch
+
+    from paper_2505_01126_amd import lbm
+
+    shape, phi0, centers, radii, nb = bubbles(n, seed, diameter)
+    L = float(n)
+    dc = centers[:, None, :] - centers[None, :, :]
+    dc -= L * np.round(dc / L)
+    dist = np.sqrt((dc * dc).sum(-1)) + np.eye(nb) * 1e9
+    keep = np.nonzero(dist.min(1) >= 2 * window + 2)[0]
+    dev = torch.device("cuda")
+    o = torch.arange(-window, window + 1, device=dev)
+    oz, oy, ox = [t.reshape(-1) for t in torch.meshgrid(o, o, o, indexing="ij")]
+    c = torch.tensor(centers[keep], device=dev, dtype=torch.float64)
+    ci = torch.round(c).long()
+    X, Y, Z = [(ci[:, a, None] + off) % n for a, off in ((0, ox), (1, oy), (2, oz))]
+    idx = (Z * n + Y) * n + X
+    d2 = 0.0
+    for a, coord in enumerate((X, Y, Z)):
+        dd = coord.double() - c[:, a, None]
+        dd -= L * torch.round(dd / L)
+        d2 = d2 + dd * dd
+    d = torch.sqrt(d2)
+    ball, core, shell = d <= window, d <= 1.0, (d >= 8.0) & (d <= 10.0)
+    g = lbm.Lattice(shape, 0.515, phi0=phi0, storage="f32", curv_mode=curv, mlp_k_lo=k_lo, mlp_k_hi=k_hi,
+                    **TWO_PHASE)
+    if curv == "mlp":
+        g.set_mlp(w16)
+    out, done = [], 0
+    for cp in checkpoints:
+        g.step(cp - done)
+        done = cp
+        m = g.moments()
+        phi = m["phi"].reshape(-1)[idx]
+        p = m["p"].reshape(-1)[idx].double()
+        reff = (3.0 * ((1.0 - phi) * ball).sum(1) / (4.0 * math.pi)).clamp(min=0.0) ** (1.0 / 3.0)
+        dp = (p * core).sum(1) / core.sum(1) - (p * shell).sum(1) / shell.sum(1)
+        e = (dp / (2.0 * TWO_PHASE["sigma"] / reff.clamp(min=1e-3)) - 1.0).cpu().numpy()
+        r = reff.cpu().numpy()
+        umag = torch.sqrt((m["u"].reshape(3, -1)[:, idx] ** 2).sum(0))
+        out.append({"steps": cp, "bubbles_measured": int(len(keep)), "mean_err": float(e.mean()),
+                    "mean_abs_err": float(np.abs(e).mean()), "max_abs_err": float(np.abs(e).max()),
+                    "r_eff_min": float(r.min()), "r_eff_max": float(r.max()),
+                    "max_u_measured": float(umag[ball].max()), "max_u": float(m["u"].abs().max()),
+                    "nonfinite": int(g.reduce()[9])})
+        del m
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def small_bubble_leg(steps, warmup, repeats, n=512, accuracy_steps=1000):
     """The same workload with 256 bubbles of d in [4, 6] (seeded): a step costs
-    the same bytes, but far more cells take the learned-curvature branch."""
+    the same bytes, but far more cells take the learned-curvature branch.
+    Beside the timings: Laplace's law on these bubbles at rest, finite
+    differences against the trained network's blend (bubble_laplace)."""
     shape, phi0, u0, params, nb = workload(n, seed=0, diameter=(4.0, 6.0))
     N = shape[0] * shape[1] * shape[2]
     out = {"bubbles": nb, "diameter": [4.0, 6.0], "interface_cells": int(((phi0 > 0.02) & (phi0 < 0.98)).sum())}
@@ -220,6 +313,19 @@ def small_bubble_leg(steps, warmup, repeats, n=512):
         ms, r0, r1 = time_variant(shape, phi0, u0, params, st, steps, warmup, repeats, 0.515, 0, curv, phs, rk3)
         out[key] = {"ms_per_step": ms, "mlups": N / (ms * 1e-3) / 1e6, "nonfinite": int(r1[9])}
         print(f"# small bubbles {key}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    del phi0, u0
+    if accuracy_steps > 0:
+        acc = {}
+        w16 = trained_weights()
+        for name, kw in (("fd", {}), ("mlp", {"curv": "mlp", "w16": w16}),
+                         ("mlp_ramp_0.2_0.3", {"curv": "mlp", "w16": w16, "k_lo": 0.2, "k_hi": 0.3})):
+            acc[name] = bubble_laplace(n, checkpoints=(accuracy_steps,), **kw)[-1]
+            a = acc[name]
+            print(f"# small bubbles at rest, {name}, {accuracy_steps} steps: Laplace error mean {a['mean_err']:+.3f}, "
+                  f"mean |e| {a['mean_abs_err']:.3f} over {a['bubbles_measured']} bubbles, max|u| {a['max_u_measured']:.2e} "
+                  f"near them ({a['max_u']:.2e} in the box)",
+                  file=sys.stderr, flush=True)
+        out["laplace_at_rest"] = acc
     return out
 
 

@@ -4,16 +4,31 @@ Recipe (seeded): periodic boxes holding a few non-overlapping spheres of the
 phi = 1 phase (droplets) or of the phi = 0 phase (bubbles) with radii drawn in
 [r_min, r_max]; the coupled solver relaxes each box (static, density ratio 1,
 tau = 1) so the interface takes the method's own discrete profile; interface
-cells are harvested with the curvature label -2/R (droplet) or +2/R (bubble),
-R the volume-equivalent radius of the relaxed sphere, and the radial normal.
+cells are harvested with the radial normal and a curvature label.
+
+The label is the curvature that makes the surface-tension force of Eq. (8)
+carry the Laplace jump of the relaxed sphere: along a ray through the
+interface the force integrates to dp = (3 delta / 2) sigma K int |grad phi|^2 dr
+for a K constant across the band, so K = (2 / R_eff) / I with
+I = (3 delta / 2) int |grad phi|^2 dr, R_eff the volume-equivalent radius.  I
+is 1 for the planar tanh profile and smaller on small relaxed spheres (about
+0.8 at R_eff = 3.5); it is taken over each sphere's cells as
+(3 delta / 2) sum |grad phi|^2 / (4 pi r^2), with the lattice gradient of the
+method (Sec. 2.3) and r the distance to the sphere's centre.  With
+label="geometric" the label is the curvature 2 / R_eff itself.  The sign is
+-1 for a phi = 1 sphere (droplet) and +1 for a phi = 0 sphere (bubble).
 Training runs the library's FP16 MFMA forward/backward and Adam kernels.
 
 Usage: python -m paper_2505_01126_amd.train_curvature [--out weights.npy]
+(default: curvature_mlp.npy beside this module, the fp16 weights that the
+benchmark's learned-curvature variants load).
 """
 from __future__ import annotations
 
 import argparse
+import itertools
 import math
+import os
 import sys
 
 import numpy as np
@@ -40,12 +55,18 @@ def _sphere_field(shape, centers, radii, width, bubbles):
     return 1.0 - phi_in if bubbles else phi_in
 
 
-def _place(rng, box, per_box, r_min, r_max, width):
+def _place(rng, box, per_box, r_min, r_max, width, radius_law="inverse"):
+    """Non-overlapping spheres; radii uniform in [r_min, r_max] ("uniform") or
+    with 1/R uniform ("inverse", density proportional to 1/R^2: a sphere's
+    interface cells grow as R^2, so every radius interval then contributes
+    about as many training rows)."""
+    if radius_law not in ("uniform", "inverse"):
+        raise ValueError(f"unknown radius law {radius_law!r}")
     centers, radii = [], []
     tries = 0
     while len(radii) < per_box and tries < 10000:
         tries += 1
-        r = rng.uniform(r_min, r_max)
+        r = rng.uniform(r_min, r_max) if radius_law == "uniform" else 1.0 / rng.uniform(1.0 / r_max, 1.0 / r_min)
         c = rng.uniform(0, box, 3)
         ok = True
         for c2, r2 in zip(centers, radii):
@@ -60,37 +81,79 @@ def _place(rng, box, per_box, r_min, r_max, width):
     return np.array(centers), np.array(radii)
 
 
-def relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device="cuda:0"):
+def lattice_gradient(phi):
+    """The isotropic lattice gradient of Sec. 2.3, 3 sum_i w_i phi(x + c_i) c_i
+    (D3Q27 weights, periodic), of an FP64 field [nz, ny, nx]; components x, y, z."""
+    w1 = {-1: 1.0 / 6.0, 0: 2.0 / 3.0, 1: 1.0 / 6.0}
+    g = np.zeros((3,) + phi.shape)
+    for cz in (-1, 0, 1):
+        for cy in (-1, 0, 1):
+            for cx in (-1, 0, 1):
+                w = w1[cx] * w1[cy] * w1[cz]
+                shifted = np.roll(phi, (-cz, -cy, -cx), axis=(0, 1, 2))  # phi(x + c)
+                for a, c in enumerate((cx, cy, cz)):
+                    if c:
+                        g[a] += 3.0 * w * c * shifted
+    return g
+
+
+def _owners(shape, centers):
+    """Index of the nearest centre (periodic) and the squared distance to it, per cell."""
+    z, y, x = I.grid(shape)
+    nz, ny, nx = shape
+    owner = np.zeros(shape, dtype=np.int64)
+    best = np.full(shape, np.inf)
+    for k, c in enumerate(centers):
+        d2 = 0.0
+        for coord, ck, n in ((x, c[0], nx), (y, c[1], ny), (z, c[2], nz)):
+            dd = coord - ck
+            dd = dd - n * np.round(dd / n)
+            d2 = d2 + dd * dd
+        better = d2 < best
+        owner = np.where(better, k, owner)
+        best = np.where(better, d2, best)
+    return owner, best
+
+
+def csf_integral(phi, centers, width=PARAMS["width"]):
+    """I = (3 delta / 2) int |grad phi|^2 dr across each sphere's interface,
+    from the sphere's cells as (3 delta / 2) sum |grad phi|^2 / (4 pi r^2)."""
+    owner, d2 = _owners(phi.shape, centers)
+    g2 = (lattice_gradient(phi) ** 2).sum(axis=0)
+    w = g2 / (4.0 * math.pi * np.maximum(d2, 0.25))
+    return np.array([1.5 * width * w[owner == k].sum() for k in range(len(centers))])
+
+
+def relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device="cuda:0", radius_law="uniform"):
     """One periodic box of spheres relaxed by the coupled solver.  Returns the
     device Lattice (caller closes it), the FP64 phase field, the centres and
     the signed volume-equivalent radii (negative for bubbles)."""
     shape = (box, box, box)
-    centers, radii = _place(rng, box, per_box, r_min, r_max, PARAMS["width"])
+    centers, radii = _place(rng, box, per_box, r_min, r_max, PARAMS["width"], radius_law)
     phi0 = _sphere_field(shape, centers, radii, PARAMS["width"], bubbles)
     g = lbm.Lattice(shape, 1.0, phi0=phi0, device=device, **PARAMS)
     g.step(relax)
     phi = g.moments()["phi"].cpu().numpy()
     # volume-equivalent radius of each relaxed sphere (Voronoi by nearest centre)
-    z, y, x = I.grid(shape)
-    owner = np.zeros(shape, dtype=np.int64)
-    best = np.full(shape, np.inf)
-    for k, c in enumerate(centers):
-        d2 = 0.0
-        for a, coord in enumerate((x, y, z)):
-            dd = coord - c[a]
-            dd = dd - box * np.round(dd / box)
-            d2 = d2 + dd * dd
-        better = d2 < best
-        owner = np.where(better, k, owner)
-        best = np.where(better, d2, best)
+    owner, _ = _owners(shape, centers)
     inside = (1.0 - phi) if bubbles else phi
     reff = np.array([(3.0 * float(inside[owner == k].sum()) / (4.0 * math.pi)) ** (1.0 / 3.0)
                      for k in range(len(centers))])
     return g, phi, centers, (-reff if bubbles else reff)
 
 
-def generate(n_boxes=24, box=48, per_box=4, r_min=2.0, r_max=10.0, relax=300, seed=0, device="cuda:0",
-             verbose=True):
+def label_radii(phi, centers, signed, label="laplace"):
+    """Signed radii to hand to the harvest so that its label -2/R (droplet) or
+    +2/R (bubble) is the training label: R_eff I ("laplace") or R_eff ("geometric")."""
+    if label == "geometric":
+        return np.asarray(signed, dtype=np.float64)
+    if label != "laplace":
+        raise ValueError(f"unknown label {label!r}")
+    return np.asarray(signed, dtype=np.float64) * csf_integral(phi, centers)
+
+
+def generate(n_boxes=48, box=48, per_box=4, r_min=2.0, r_max=10.0, relax=300, seed=0, device="cuda:0",
+             verbose=True, label="laplace", radius_law="inverse"):
     """Harvest training rows from relaxed method-generated spheres.
     Returns device tensors X [n, 32] (fp16 bits) and Y [n, 4] (FP32)."""
     import torch
@@ -99,8 +162,8 @@ def generate(n_boxes=24, box=48, per_box=4, r_min=2.0, r_max=10.0, relax=300, se
     Xs, Ys = [], []
     for b in range(n_boxes):
         bubbles = bool(b % 2)
-        g, _, centers, signed = relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device)
-        X, Y, n = g.harvest(centers, signed, cap=1 << 20)
+        g, phi, centers, signed = relaxed_box(rng, box, per_box, r_min, r_max, relax, bubbles, device, radius_law)
+        X, Y, n = g.harvest(centers, label_radii(phi, centers, signed, label), cap=1 << 20)
         Xs.append(X.clone())
         Ys.append(Y.clone())
         g.close()
@@ -122,18 +185,67 @@ def init_weights(seed=0):
     return w.astype(np.float16).astype(np.float64)
 
 
-def train(X, Y, steps=3000, batch=4096, lr=2e-3, seed=0, device="cuda:0", log_every=500):
-    """Adam on minibatches drawn with a seeded generator; returns (Mlp, losses)."""
+def cube_symmetries():
+    """The 48 rotations and reflections of the cube acting on a training row:
+    (column maps [48, 32], label maps [48, 4], label signs [48, 4]).  Symmetry
+    t sends the stencil offset o to o' with o'_a = s_a o_p(a); the transformed
+    row takes X'[:, j] = X[:, cols[t, j]] (the 5 padding columns stay) and
+    Y'[:, k] = Y[:, ycols[t, k]] * ysign[t, k] (K unchanged, the normal rotated)."""
+    offs = [(i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1) for i in range(27)]
+    cols, ycols, ysign = [], [], []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            inv = list(range(32))
+            for i, o in enumerate(offs):
+                t = [signs[a] * o[perm[a]] for a in range(3)]
+                inv[(t[0] + 1) + 3 * (t[1] + 1) + 9 * (t[2] + 1)] = i
+            cols.append(inv)
+            ycols.append([0] + [1 + perm[a] for a in range(3)])
+            ysign.append([1.0] + [float(signs[a]) for a in range(3)])
+    return np.array(cols), np.array(ycols), np.array(ysign)
+
+
+def stencil_grad2(X):
+    """|grad phi|^2 of each training row from its 27 fp16 inputs 2 phi - 1 (the
+    lattice gradient of Sec. 2.3), as a device FP32 tensor."""
+    import torch
+
+    w1 = {-1: 1.0 / 6.0, 0: 2.0 / 3.0, 1: 1.0 / 6.0}
+    cw = [[1.5 * w1[i % 3 - 1] * w1[(i // 3) % 3 - 1] * w1[i // 9 - 1] * (i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1)[a]
+           for a in range(3)] for i in range(27)]  # 3 w_i c_i / 2: the inputs are 2 phi - 1
+    g = X[:, :27].view(torch.float16).float() @ torch.tensor(cw, dtype=torch.float32, device=X.device)
+    return (g * g).sum(1)
+
+
+def train(X, Y, steps=4000, batch=4096, lr=2e-3, seed=0, device="cuda:0", log_every=500, importance=True,
+          augment=True):
+    """Adam on minibatches drawn with a seeded generator; returns (Mlp, losses).
+    importance: rows drawn with probability proportional to |grad phi|^2, the
+    weight of a cell's curvature in the surface-tension force (an unweighted
+    draw spends most of the fit on the faint tails of the interface band);
+    augment: each drawn row turned by a random one of the 48 cube symmetries."""
     import torch
 
     net = lbm.Mlp(init_weights(seed), device=device)
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     n = X.shape[0]
+    prob = stencil_grad2(X) if importance else None
+    if augment:
+        cols, ycols, ysign = (torch.tensor(a, device=device) for a in cube_symmetries())
+        ysign = ysign.float()
     losses = []
     for it in range(1, steps + 1):
-        idx = torch.randint(0, n, (min(batch, n),), device=device, generator=gen)
-        _, loss = net.backward(X[idx].contiguous(), Y[idx].contiguous())
+        if prob is not None:
+            idx = torch.multinomial(prob, batch, replacement=True, generator=gen)
+        else:
+            idx = torch.randint(0, n, (min(batch, n),), device=device, generator=gen)
+        xb, yb = X[idx], Y[idx]
+        if augment:
+            t = torch.randint(0, 48, (idx.shape[0],), device=device, generator=gen)
+            xb = torch.gather(xb, 1, cols[t])
+            yb = torch.gather(yb, 1, ycols[t]) * ysign[t]
+        _, loss = net.backward(xb.contiguous(), yb.contiguous())
         step_lr = lr * (0.5 * (1.0 + math.cos(math.pi * it / steps)))  # cosine decay
         net.adam(lr=step_lr)
         if it % log_every == 0 or it == 1:
@@ -144,14 +256,14 @@ def train(X, Y, steps=3000, batch=4096, lr=2e-3, seed=0, device="cuda:0", log_ev
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="curvature_mlp.npy")
-    ap.add_argument("--boxes", type=int, default=24)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "curvature_mlp.npy"))
+    ap.add_argument("--boxes", type=int, default=48)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
     X, Y = generate(n_boxes=a.boxes, seed=a.seed)
     net, losses = train(X, Y, steps=a.steps, seed=a.seed)
-    np.save(a.out, net.weights_fp16())
+    np.save(a.out, net.weights_fp16().astype(np.float16))
     print(f"saved {a.out}; final loss {losses[-1][1]:.3e}")
 
 

@@ -1,18 +1,25 @@
 """What the learned curvature gains over the finite-difference curvature.
 
-The network (27 -> 64 -> 64 -> 4, FP16 MFMA training kernels) is trained on
-droplets and bubbles that the coupled solver relaxes, labelled with the
-curvature -+2/R_eff of the sphere each interface cell belongs to (R_eff the
-volume-equivalent radius).  The finite-difference curvature of a cell is the
-curvature of the cell's own level set, about 2/r at distance r from the
-centre, so across the diffuse band it is biased whenever R is not large
-against the interface width.  Evaluated on spheres the network has not seen
-(other seeds):
+The network (27 -> 64 -> 64 -> 4, FP16 MFMA training kernels) is trained with
+train_curvature's default recipe: 48 periodic 48^3 boxes of 4 droplets or
+bubbles with radii in [2, 10] (1/R uniform, so small spheres contribute as
+many interface cells as large ones), relaxed by the coupled solver and
+harvested with the Laplace-consistent curvature label K = (2 / R_eff) / I (I
+the integral of the surface-tension profile across the relaxed sphere);
+4000 Adam steps on rows drawn in proportion to |grad phi|^2 and turned by
+random cube symmetries.  It is evaluated on spheres it has not seen:
 
-1. curvature error at the interface cells against the label, network vs
-   finite differences (the oracle's FP64 curvature of the same relaxed field);
-2. Laplace's law on relaxed droplets, pressure jump vs 2 sigma / R_eff, with
-   the learned blend in the step vs the finite-difference force.
+1. the Laplace jump that the surface-tension force of Eq. (8) carries across
+   each held-out relaxed sphere, (3 delta / 2) sigma sum K |grad phi|^2 /
+   (4 pi r^2) over its interface cells, against 2 sigma / R_eff, with the
+   network's K and with the finite-difference K (the oracle's FP64 curvature
+   of the same field);
+2. Laplace's law on droplets of R = 3, 4, 6 (diameters 6 to 12, the
+   under-resolved range) relaxed for 1500 steps by the coupled solver with the
+   learned blend on the ramp |K_FD| from 0.2 to 0.3, against the
+   finite-difference run, at density ratio 1 and 10, with a bound on the
+   spurious currents.  R = 2.5 is printed, not asserted: there the blend loses
+   to finite differences at both density ratios.
 
 Parity of the kernels themselves is covered by test_gpu_mlp.py.
 """
@@ -25,54 +32,57 @@ import oracle as O
 from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
+SIGMA = 0.01
+K_LO, K_HI = 0.2, 0.3  # the blend ramp on |K_FD| (the library's default is 0.4 .. 0.6)
+CAPILLARY_U = SIGMA / (1.0 * (1.0 - 0.5) / 3.0)  # sigma / (rho_l nu) at tau = 1
 
 
 @pytest.fixture(scope="module")
 def trained():
     from paper_2505_01126_amd import train_curvature as tc
 
-    X, Y = tc.generate(n_boxes=12, box=40, per_box=3, r_min=2.5, r_max=8.0, relax=300, seed=0, verbose=False)
-    net, losses = tc.train(X, Y, steps=2000, seed=0, log_every=1000)
+    X, Y = tc.generate(seed=0, verbose=False)
+    net, losses = tc.train(X, Y, seed=0, log_every=2000)
     print(f"training rows {X.shape[0]}, loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}")
-    assert losses[-1][1] < 0.1 * losses[0][1]
+    assert losses[-1][1] < 0.01 * losses[0][1]
     return net
 
 
-def test_learned_curvature_beats_fd_on_unseen_spheres(trained):
-    import torch
-
+def test_learned_curvature_carries_the_laplace_jump_of_unseen_spheres(trained):
     from paper_2505_01126_amd import train_curvature as tc
 
     rng = np.random.default_rng(1234)
-    e_fd, e_net, wts, n_rows = [], [], [], 0
-    for b, bubbles in enumerate((False, True, False, True)):
+    rows = []
+    for bubbles in (False, True, False, True):
         g, phi, centers, signed = tc.relaxed_box(rng, 40, 3, 3.0, 7.0, 300, bubbles)
-        X, Y, n = g.harvest(centers, signed, cap=1 << 20)
+        X, _, n = g.harvest(centers, signed, cap=1 << 20)
         g.close()
         mask = (phi > 0.02) & (phi < 0.98)  # the harvested cells, in site order
         assert n == int(mask.sum())
-        k_label = Y[:, 0].double().cpu().numpy()
-        k_net = trained.forward(X).double().cpu().numpy()[:, 0]
-        k_fd = O.curvature(phi)[0][mask]
-        g = O.gradient(phi)
-        e_fd.append(np.abs(k_fd - k_label))
-        e_net.append(np.abs(k_net - k_label))
-        wts.append((g ** 2).sum(axis=0)[mask])  # |grad phi|^2: the weight of K in the force
-        n_rows += n
-    e_fd, e_net, wts = np.concatenate(e_fd), np.concatenate(e_net), np.concatenate(wts)
-    wfd, wnet = (wts * e_fd).sum() / wts.sum(), (wts * e_net).sum() / wts.sum()
-    print(f"{n_rows} interface cells: mean |K - K_label| FD {e_fd.mean():.4f}, network {e_net.mean():.4f}; "
-          f"|grad phi|^2-weighted FD {wfd:.4f}, network {wnet:.4f}")
-    assert e_net.mean() < 0.75 * e_fd.mean()
-    assert wnet < 0.75 * wfd
+        k_net = np.abs(trained.forward(X).double().cpu().numpy()[:, 0])
+        k_fd = np.abs(O.curvature(phi)[0][mask])
+        g2 = (O.gradient(phi) ** 2).sum(axis=0)[mask]
+        owner, d2 = tc._owners(phi.shape, centers)
+        owner, w = owner[mask], g2 / (4.0 * math.pi * np.maximum(d2[mask], 0.25))
+        for k, r in enumerate(np.abs(signed)):
+            sel = owner == k
+            jump = lambda K: 1.5 * 4.0 * float((K[sel] * w[sel]).sum()) / (2.0 / r) - 1.0  # noqa: E731
+            rows.append((r, jump(k_net), jump(k_fd)))
+    rows = np.array(rows)
+    for r, en, ef in rows:
+        print(f"R_eff {r:.2f}: force-carried jump / (2 sigma / R_eff) - 1: network {en:+.4f}, FD {ef:+.4f}")
+    e_net, e_fd = np.abs(rows[:, 1]).mean(), np.abs(rows[:, 2]).mean()
+    print(f"{len(rows)} spheres: mean |error| network {e_net:.4f}, FD {e_fd:.4f}")
+    assert e_net < 0.5 * e_fd
 
 
-def _laplace_error(mode, R, ratio, w16, n=32, steps=1500, sigma=0.01):
+def _laplace(mode, R, ratio, w16, n=32, steps=1500):
     from paper_2505_01126_amd import lbm
 
     phi0, c = I.droplet((n, n, n), R, 4.0, seed=int(R * 10))
-    g = lbm.Lattice((n, n, n), 1.0, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=sigma, mobility=0.05,
-                    width=4.0, p0=0.0, curv_mode=mode)
+    print(f"case Laplace {mode} R={R} ratio={ratio}", flush=True)
+    g = lbm.Lattice((n, n, n), 1.0, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=SIGMA, mobility=0.05,
+                    width=4.0, p0=0.0, curv_mode=mode, mlp_k_lo=K_LO, mlp_k_hi=K_HI)
     if mode == "mlp":
         g.set_mlp(w16)
     g.step(steps)
@@ -84,15 +94,17 @@ def _laplace_error(mode, R, ratio, w16, n=32, steps=1500, sigma=0.01):
     d = np.sqrt(((x - c[0] + n / 2) % n - n / 2) ** 2 + ((y - c[1] + n / 2) % n - n / 2) ** 2 +
                 ((z - c[2] + n / 2) % n - n / 2) ** 2)
     dp = p[d < 1.5].mean() - p[d > R + 12].mean()
-    return dp / (2.0 * sigma / reff) - 1.0, np.abs(m["u"]).max()
+    return dp / (2.0 * SIGMA / reff) - 1.0, np.abs(m["u"]).max()
 
 
 @pytest.mark.parametrize("ratio", [1.0, 10.0])
 def test_learned_curvature_improves_laplace_law(trained, ratio):
-    for R in (3.0, 4.0, 6.0):
-        efd, ufd = _laplace_error("fd", R, ratio, None)
-        enet, unet = _laplace_error("mlp", R, ratio, trained.w16)
+    for R in (2.5, 3.0, 4.0, 6.0):
+        efd, ufd = _laplace("fd", R, ratio, None)
+        enet, unet = _laplace("mlp", R, ratio, trained.w16)
         print(f"ratio {ratio:g} R {R:g}: Laplace error FD {efd:+.4f} (max|u| {ufd:.1e}), "
-              f"learned {enet:+.4f} (max|u| {unet:.1e})")
-        if R >= 4.0:
+              f"learned {enet:+.4f} (max|u| {unet:.1e}, {unet / ufd:.1f}x FD)")
+        if R >= 3.0:
             assert abs(enet) < abs(efd)
+        # spurious currents: bounded against the FD run and the capillary velocity
+        assert unet < 25.0 * ufd and unet < 0.1 * CAPILLARY_U
