@@ -134,9 +134,17 @@ size_t lbm_workspace_bytes(const lbm_config *cfg);
 int lbm_init(lbm_handle **out, const lbm_config *cfg, void *d_ws, size_t ws_bytes, const double *d_phi0,
              const double *d_u0, const double *d_pstar0, void *stream);
 
-/* Advance nsteps >= 0 time steps: one fused kernel launch per step, plus the
- * learned-curvature network pass ahead of it (LBM_CURV_MLP) and two more
- * phase-field stages after it (ac_rk3); pairs of steps replay a captured graph. */
+/* Advance nsteps >= 0 time steps of the coupled scheme: per step, the pull
+ * streaming of the populations (Sec. 2.2, Eq. 4), their moments, the
+ * surface-tension, pressure and viscous forces (Sec. 2.3, Eq. 8) with the
+ * velocity u = j + a/2, the regularised collision (Sec. 2.2, Eqs. 6-7) and the
+ * conservative Allen-Cahn update of phi (Sec. 2.1, Eq. 3; WENO-5 convection).
+ * One fused kernel launch per step, plus the learned-curvature network pass
+ * ahead of it (LBM_CURV_MLP) and two more phase-field stages after it
+ * (ac_rk3); pairs of steps replay a captured graph.  Asynchronous on the
+ * handle's stream; the state stays in the caller's workspace.  Returns
+ * LBM_EINVAL (NULL handle or nsteps < 0), LBM_ESTATE (LBM_CURV_MLP before
+ * lbm_set_mlp), LBM_EHIP (launch failure, text in lbm_last_error). */
 int lbm_step(lbm_handle *h, int64_t nsteps);
 
 /* Fields at the current time n, written to caller device buffers; any pointer
@@ -145,7 +153,10 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
  * storage). */
 int lbm_moments(lbm_handle *h, float *d_rho, float *d_p, float *d_u, double *d_phi);
 
-/* Global FP64 statistics at time n (deterministic order of summation):
+/* Global FP64 statistics at time n: the conserved phase volume sum phi that
+ * the conservative Allen-Cahn form keeps constant (Sec. 2.1, Eq. 3), and the
+ * mass, momentum and kinetic-energy sums of the flow (the energy budget of the
+ * forced turbulence of Sec. 5.1), in a deterministic order of summation:
  *   out[0] sum phi, [1] sum rho, [2] sum p*, [3..5] sum rho u, [6] 1/2 sum rho |u|^2,
  *   [7] max |u|, [8] max overshoot of phi outside [0, 1], [9] sites with a non-finite
  *   p*, u or phi.
