@@ -616,21 +616,19 @@ __device__ __forceinline__ void lds_barrier()
 // else: phi_out = rk_a phi^n + rk_b (phi_in + L(phi_in)) with phi_in staged in
 // the LDS ring (B.phin), phi^n read at the site (B.phin0), FP64 phi.
 template <int S, bool TP, bool FRC, bool ML, int TW = TX, bool LATE_PF = (S == 0), bool FX = false,
-          bool ACO = false, bool PH = false, bool PRE = false>
+          bool ACO = false, bool PH = false>
 __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, const uint32_t L, double rk_a = 0.0,
                                           double rk_b = 1.0)
 {
     static_assert(!ACO || (TP && !FX && !ML), "a Runge-Kutta stage needs the FP64 phase field");
-    static_assert(!PRE || (TP && ML && !ACO), "the network pass belongs to the learned curvature");
-    // PRE: the learned-curvature pass that runs before the step: at every
-    // interface cell (0.02 < phi < 0.98) it leaves in B.mlpy (float4 per site)
-    // the network output where the curvature criterion selects the cell and
-    // NaN elsewhere; nothing else.  The step with ML set reads it where its own
-    // criterion selects the cell (the same test on the same stencil, so the
-    // pass has written there) and falls back to finite differences on NaN, so
-    // the network's registers and LDS are not part of the step kernel.
-    constexpr bool NET = ML && PRE;  // the network is evaluated in this kernel
-    constexpr bool LBM = !ACO && !PRE;  // the populations are streamed and collided
+    // ML: the learned curvature.  The network pass (pass_tile) that runs
+    // before the step leaves in B.mlpy the network output at every interface
+    // cell that the curvature criterion selects (NaN at the other interface
+    // cells); the step reads it where its own criterion selects the cell (the
+    // same test on the same stencil, so the pass has written there) and falls
+    // back to finite differences on NaN, so the network's registers and LDS
+    // are not part of the step kernel.
+    constexpr bool LBM = !ACO;  // the populations are streamed and collided
     using T = typename Pop<S>::T;
     using PS = PhiStore<FX>;
     using PT = typename PS::T;
@@ -661,22 +659,6 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // unconditional, so the compiler counts the loads in flight exactly instead
     // of draining all of them (stores included) before the next plane.
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
-    if constexpr (PRE) {
-        // the network pass skips a work item none of whose sites is an
-        // interface cell (the step leaves nothing to read there): its flags are
-        // the x-segments of its rows in its planes
-        if (B.iflag) {
-            const int nseg = flag_segments(nx);
-            const int s0 = x0 / 32, ns = min((x0 + TXW + 31) / 32, nseg) - s0;
-            const int nr = min(TYW, ny - y0), np = zend - z0;
-            bool any = false;
-            for (int e = tid; e < ns * nr * np; e += NTHREADS) {
-                const int si = e % ns, r = (e / ns) % nr, k = e / (ns * nr);
-                any |= B.iflag[((size_t)(z0 + k) * ny + (y0 + r)) * nseg + s0 + si] != 0;
-            }
-            if (!__syncthreads_or(any)) return;
-        }
-    }
     // every tile row of populations, u and phi fills whole 128-byte lines
     const bool nt_rows = (TW * ES) % 128 == 0 && nx % 64 == 0;
     const T *__restrict__ fin = (const T *)B.fin;
@@ -738,16 +720,11 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // LDS: phi ring (FP32), Q planes z-1..z+1, x/y face fluxes of plane z, and
     // the global xy offset of every position of the phi tile
     __shared__ float sphi[TP ? NRING : 1][TP ? PLANE : 1];
-    constexpr bool AC = TP && !PRE;  // the Allen-Cahn update runs here
+    constexpr bool AC = TP;  // the Allen-Cahn update runs here
     __shared__ float4 sq[AC ? 3 : 1][AC ? QPLANE : 1];  // Q (x, y, z, unused) per point
     __shared__ float sjx[AC ? NXF : 1];
     __shared__ float sjy[AC ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
-    // learned curvature: weights and per-wave scratch
-    __shared__ char mlp_raw[NET ? sizeof(MlpW) + (NTHREADS / 64) * sizeof(MlpWave) : 1];
-    MlpW &smw = *(MlpW *)mlp_raw;
-    MlpWave *smwave = (MlpWave *)(mlp_raw + (NET ? sizeof(MlpW) : 0));
-    if constexpr (NET) load_weights(gconst((const uint16_t *)P.mlp), smw, tid, NTHREADS);
     int q_lds[QPTS];
     int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
     bool f_isx[FROUNDS];
@@ -860,7 +837,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         }
         fetch_plane(z0 + 3);
         lds_barrier();
-        if constexpr (!PRE) {
+        {
             fetch_face_u(z0);
             compute_q(z0 - 1);
             compute_q(z0);
@@ -889,11 +866,9 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             store_plane(z + 3);
             fetch_plane(zn + 3);
             lds_barrier();
-            if constexpr (!PRE) {
-                compute_q(z + 1);
-                compute_faces(z);
-                fetch_face_u(zn);
-            }
+            compute_q(z + 1);
+            compute_faces(z);
+            fetch_face_u(zn);
             lds_barrier();
         }
         const uint32_t own = (uint32_t)z * plane + own_xy;
@@ -902,37 +877,6 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
         float ph[27];
         float kfd = 0.f, gn = 0.f;
         bool sel = false;
-        if constexpr (PRE) {
-            // the learned-curvature pass: stencil and criterion, only in waves
-            // that hold an interface cell (most waves hold none)
-            const float *pm = sphi[ring(z - 1)];
-            const float *pc = sphi[ring(z)];
-            const float *pp = sphi[ring(z + 1)];
-            const float c0 = pc[lc];
-            const bool cand = c0 > 0.02f && c0 < 0.98f;
-            float y[4] = {0.f, 0.f, 0.f, 0.f};
-            if (__ballot(cand) != 0ull) {
-                if (cand) {
-#pragma unroll
-                    for (int i = 0; i < 27; i++) {
-                        const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
-                        ph[i] = pl[lc + CY(i) * PX + CX(i)];
-                    }
-                    phi_stencil(ph, G);
-                    sel = mlp_select(G, P, kfd, gn);
-                }
-                mlp_wave(smw, smwave[tid >> 6], sel, ph, y, tid & 63);
-            }
-            if (cand) {
-                const float nan = __builtin_nanf("");
-                LBM_GLOBAL float *yo = gmut((float *)B.mlpy) + 4 * (size_t)own;
-                yo[0] = sel ? y[0] : nan;
-                yo[1] = sel ? y[1] : nan;
-                yo[2] = sel ? y[2] : nan;
-                yo[3] = sel ? y[3] : nan;
-            }
-            continue;
-        }
         float aext[3] = {0.f, 0.f, 0.f};
         float y[4] = {0.f, 0.f, 0.f, 0.f};  // learned curvature: network output at a selected cell
         {
@@ -1077,6 +1021,140 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     }
 }
 
+// The learned-curvature pass over one work item, ahead of the step: at every
+// interface cell (0.02 < phi < 0.98) it leaves in B.mlpy (float4 per site) the
+// network output where the curvature criterion selects the cell and NaN
+// elsewhere.  The 3^3 stencil needs phi at halo 1 only, so the pass stages a
+// (TW + 2) x (256/TW + 2) tile in a four-plane ring (the step stages halo 3 and
+// seven planes for WENO-5): half the phi bytes per item.  The staged values,
+// the stencil and the criterion are the step's, so the step selects exactly
+// the cells written here.  A work item none of whose sites is an interface
+// cell is skipped: its flags are the x-segments of its rows in its planes.
+// W: the weights in LDS; *loaded: the weights W holds (reloaded when a box of
+// the batch brings others).
+template <int TW, bool FX>
+__device__ __forceinline__ void pass_tile(const Params &P, const Buffers &B, const uint32_t L, MlpW &W,
+                                          MlpWave *wave_lds, const void *&loaded)
+{
+    using PS = PhiStore<FX>;
+    using PT = typename PS::T;
+    constexpr int TXW = TW, TYW = NTHREADS / TW;
+    constexpr int PX = TXW + 2, PY = TYW + 2, PLANE = PX * PY;
+    constexpr int LOADS = (PLANE + NTHREADS - 1) / NTHREADS;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TXW + tx;
+    const int bx = (int)(L % (uint32_t)P.gx), by = (int)((L / (uint32_t)P.gx) % (uint32_t)P.gy);
+    const int bz = (int)(L / ((uint32_t)P.gx * (uint32_t)P.gy));
+    const int x0 = bx * TXW, y0 = by * TYW, z0 = bz * P.zchunk;
+    const int zend = min(z0 + P.zchunk, nz);
+    // lanes past a ragged box edge evaluate the periodic image of their site
+    // and write the owner's bits again
+    const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
+    if (B.iflag) {
+        const int nseg = flag_segments(nx);
+        const int s0 = x0 / 32, ns = min((x0 + TXW + 31) / 32, nseg) - s0;
+        const int nr = min(TYW, ny - y0), np = zend - z0;
+        bool any = false;
+        for (int e = tid; e < ns * nr * np; e += NTHREADS) {
+            const int si = e % ns, r = (e / ns) % nr, k = e / (ns * nr);
+            any |= B.iflag[((size_t)(z0 + k) * ny + (y0 + r)) * nseg + s0 + si] != 0;
+        }
+        if (!__syncthreads_or(any)) return;
+    }
+    if (P.mlp != loaded) {  // uniform: one box per work item
+        load_weights(gconst((const uint16_t *)P.mlp), W, tid, NTHREADS);
+        loaded = P.mlp;
+    }
+    const LBM_GLOBAL PT *__restrict__ phin = gconst((const PT *)B.phin);
+    LBM_GLOBAL float *__restrict__ yout = gmut((float *)B.mlpy);
+    __shared__ float sphi[4][PLANE];
+    __shared__ uint32_t sxy[PLANE];
+#pragma unroll
+    for (int k = 0; k < LOADS; k++) {
+        const int e = tid + k * NTHREADS;
+        const int ly = e / PX, lx = e - ly * PX;
+        if (e < PLANE) sxy[e] = (uint32_t)modi(y0 + ly - 1, ny) * nx + (uint32_t)modi(x0 + lx - 1, nx);
+    }
+    __syncthreads();
+    // phi planes in flight: three register sets, each fetched three planes
+    // ahead of its store into the ring (one plane of work is too short to
+    // hide a load from memory); every fetch and store is unconditional (a
+    // plane past the chunk re-reads a valid plane) so that the compiler waits
+    // for exactly the set it stores
+    PT ra[LOADS], rb[LOADS], rc[LOADS];
+    auto fetch_plane = [&](PT(&r)[LOADS], int z) {
+        const LBM_GLOBAL PT *src = phin + (size_t)modi(z, nz) * plane;
+#pragma unroll
+        for (int k = 0; k < LOADS; k++) {
+            const int e = tid + k * NTHREADS;
+            r[k] = src[sxy[e < PLANE ? e : PLANE - 1]];  // spare lanes re-read the last point
+        }
+    };
+    auto store_plane = [&](const PT(&r)[LOADS], int z) {
+        float *dst = sphi[(z + 4) & 3];
+#pragma unroll
+        for (int k = 0; k < LOADS; k++) {
+            const int e = tid + k * NTHREADS;
+            if (e < PLANE) dst[e] = PS::f32(r[k]);
+        }
+    };
+    const int lc = (ty + 1) * PX + (tx + 1);  // own phi tile index
+    const uint32_t own_xy = (uint32_t)yg * nx + xg;
+    // stencil, criterion and network of plane z (planes z-1 .. z+1 in the ring)
+    auto compute = [&](int z) {
+        const float *pm = sphi[(z + 3) & 3];
+        const float *pc = sphi[z & 3];
+        const float *pp = sphi[(z + 1) & 3];
+        const float c0 = pc[lc];
+        const bool cand = c0 > 0.02f && c0 < 0.98f;
+        if (__ballot(cand) == 0ull) return;  // most waves hold no interface cell
+        float ph[27];
+        float y[4] = {0.f, 0.f, 0.f, 0.f};
+        bool sel = false;
+        if (cand) {
+#pragma unroll
+            for (int i = 0; i < 27; i++) {
+                const float *pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : pc);
+                ph[i] = pl[lc + CY(i) * PX + CX(i)];
+            }
+            PhiGrad G;
+            float kfd, gn;
+            phi_stencil(ph, G);
+            sel = mlp_select(G, P, kfd, gn);
+        }
+        mlp_wave(W, wave_lds[tid >> 6], sel, ph, y, tid & 63);
+        if (cand) {
+            const float nan = __builtin_nanf("");
+            LBM_GLOBAL float *yo = yout + 4 * (size_t)((uint32_t)z * plane + own_xy);
+            yo[0] = sel ? y[0] : nan;
+            yo[1] = sel ? y[1] : nan;
+            yo[2] = sel ? y[2] : nan;
+            yo[3] = sel ? y[3] : nan;
+        }
+    };
+    // plane z: plane z+1 into the ring (its slot held z-3, last read two
+    // planes ago), plane z+4 into the freed register set, one barrier
+    auto plane_step = [&](int z, PT(&r)[LOADS]) {
+        store_plane(r, z + 1);
+        fetch_plane(r, z + 4);
+        lds_barrier();
+        if (z < zend) compute(z);
+    };
+    fetch_plane(ra, z0 - 1);
+    store_plane(ra, z0 - 1);
+    fetch_plane(ra, z0);
+    store_plane(ra, z0);
+    fetch_plane(ra, z0 + 1);
+    fetch_plane(rb, z0 + 2);
+    fetch_plane(rc, z0 + 3);
+    for (int z = z0; z < zend; z += 3) {
+        plane_step(z, ra);
+        plane_step(z + 1, rb);
+        plane_step(z + 2, rc);
+    }
+}
+
 // ------------------------------------------------------------ work queue
 // The persistent loop of a batched launch over the boxes of a batch: a
 // workgroup takes the next work item from one queue counter per launch, so the
@@ -1135,8 +1213,11 @@ __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3
 k_mlp_pass_batch(const Params *__restrict__ tab, const Buffers *__restrict__ buf, const uint32_t *__restrict__ first,
                  int nbox, uint32_t *counter, int parity)
 {
+    __shared__ MlpW w_lds;
+    __shared__ MlpWave wave_lds[NTHREADS / 64];
+    const void *loaded = nullptr;
     batch_loop<TW>(first, nbox, counter, parity, [&](int b, uint32_t L) {
-        step_tile<0, true, false, true, TW, true, FX, false, false, true>(tab[b], buf[b], L);
+        pass_tile<TW, FX>(tab[b], buf[b], L, w_lds, wave_lds, loaded);
     });
 }
 
