@@ -1145,8 +1145,13 @@ __device__ __forceinline__ void pass_tile(const Params &P, const Buffers &B, con
     store_plane(ra, z0 - 1);
     fetch_plane(ra, z0);
     store_plane(ra, z0);
+    // issued in this order (the compiler would otherwise reorder the three
+    // sets, and the first wait of every pass through the loop would then
+    // cover all of them)
     fetch_plane(ra, z0 + 1);
+    asm volatile("" ::: "memory");
     fetch_plane(rb, z0 + 2);
+    asm volatile("" ::: "memory");
     fetch_plane(rc, z0 + 3);
     for (int z = z0; z < zend; z += 3) {
         plane_step(z, ra);
