@@ -233,3 +233,67 @@ def test_learned_curvature_with_moving_interface_matches_oracle():
     check(m, mo, "f32", "moving droplet, learned curvature", u_bar=1e-5 + 2.0 * e_net * dfd,
           p_bar=1e-5 + 2.0 * e_net_max * dfd_p, phi_bar=1e-5, drho=0.0)
     assert dfd > 1e-4 and zc[0] - c[2] > 2.0
+
+
+def _learned_vs_oracle(lbm, shape, phi0, u0, w, kw, steps, label, **lattice_kw):
+    """Run the learned-curvature step on the GPU and in the FP64 oracle; the
+    bars as in test_step_with_learned_curvature_matches_oracle (the network
+    output difference e_net times the network's share of the flow)."""
+    import torch
+
+    print(f"case {label}", flush=True)
+    g = lbm.Lattice(shape, 0.8, phi0=phi0, u0=u0, curv_mode="mlp", **lattice_kw, **kw)
+    g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
+    g.step(steps)
+    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    ny, nx = shape[1], shape[2]
+    X, _, n = g.harvest(np.array([[nx / 2.0, ny / 2.0, shape[0] / 2.0]]), np.array([4.0]), cap=1 << 16)
+    y_gpu = lbm.Mlp(w).forward(X).double().cpu().numpy()
+    g.close()
+    y_orc = O.mlp_forward(w, X.cpu().numpy().view(np.float16)[:, :27].astype(np.float64))
+    e_net = np.linalg.norm(y_gpu - y_orc) / np.linalg.norm(y_orc)
+    e_net_max = np.abs(y_gpu - y_orc).max() / np.abs(y_orc).max()
+    o = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, curv_mode=1, mlp=w, **kw)
+    o.step(steps)
+    mo = o.moments()
+    ofd = O.Oracle(shape, 0.8, phi0=phi0, u0=u0, **kw)
+    ofd.step(steps)
+    mfd = ofd.moments()
+    dfd = np.linalg.norm(mfd["u"] - mo["u"]) / np.linalg.norm(mo["u"])
+    dfd_p = np.abs(mfd["p"] - mo["p"]).max() / np.abs(mo["p"] - mo["p"].mean()).max()
+    print(f"{label}: network outputs differ by {e_net:.3e} on {n} cells; FD vs learned oracle runs by {dfd:.3e}")
+    check(m, mo, "f32", label, u_bar=1e-5 + 2.0 * e_net * dfd, p_bar=1e-5 + 2.0 * e_net_max * dfd_p,
+          phi_bar=1e-5, drho=kw["rho_l"] - kw["rho_g"])
+    assert dfd > 1e-4 and n > 50
+
+
+def test_learned_curvature_with_fixed_point_phi_matches_oracle():
+    """The network pass and the learned step with the int32 fixed-point phase
+    field (the pass stages phi converted from the fixed-point grid), against
+    the FP64 oracle: the quantum 2^-30 is far below the bars."""
+    lbm = _lbm()
+    shape = (24, 20, 70)
+    phi_a, _ = I.droplet(shape, 3.0, 4.0, center=(20.3, 10.1, 12.2))
+    phi_b, _ = I.droplet(shape, 4.0, 4.0, center=(52.7, 9.6, 11.4))
+    phi0 = np.maximum(phi_a, phi_b)
+    u0 = I.random_u(shape, 0.005, seed=41)
+    kw = dict(rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    _learned_vs_oracle(lbm, shape, phi0, u0, _mlp_case_weights(34), kw, 30, "learned curvature, fix32 phi",
+                       zchunk=8, phi_storage="fix32")
+
+
+def test_learned_curvature_in_a_thin_box_with_ragged_z_chunks_matches_oracle():
+    """A box eight planes thick (the smallest allowed) cut into z-chunks of
+    3, 3 and 2 planes: the network pass stages planes z0-1 .. z0+3 ahead and
+    runs its plane loop three planes at a time, so a chunk shorter than three
+    planes, the periodic wrap of the staged planes and planes fetched past the
+    chunk all occur.  The drop is a column along z, curved in x and y only."""
+    lbm = _lbm()
+    shape = (8, 24, 40)
+    z, y, x = I.grid(shape)
+    r = np.sqrt((x - 19.6) ** 2 + (y - 11.8) ** 2) + 0.0 * z
+    phi0 = I.tanh_profile(4.0 - r, 4.0)
+    u0 = I.random_u(shape, 0.005, seed=42)
+    kw = dict(rho_l=1.0, rho_g=0.5, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    _learned_vs_oracle(lbm, shape, phi0, u0, _mlp_case_weights(35), kw, 40,
+                       "learned curvature, nz = 8, z-chunks 3 3 2", zchunk=3)
