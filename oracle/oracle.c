@@ -38,9 +38,9 @@
  * the viscous correction F^nu and the phase-dependent relaxation time through
  * the steady layered flow of a variable-property momentum equation.  Several
  * of these tests compile a copy of this file with a planted mistake and show
- * that the pin catches it.
- * Parity unpinned: the one-step lag of the Allen-Cahn velocity (a reading of
- * the time integration, not a closed form).
+ * that the pin catches it.  The one-step lag of the Allen-Cahn velocity (a
+ * reading of the time integration) is pinned by a slab pushed from rest: the
+ * push reaches phi one step after the velocity that carries it.
  */
 #include "oracle.h"
 
