@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import check
+from parity import U_BAR, check
 from paper_2505_01126_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -235,14 +235,14 @@ def test_learned_curvature_with_moving_interface_matches_oracle():
     assert dfd > 1e-4 and zc[0] - c[2] > 2.0
 
 
-def _learned_vs_oracle(lbm, shape, phi0, u0, w, kw, steps, label, **lattice_kw):
+def _learned_vs_oracle(lbm, shape, phi0, u0, w, kw, steps, label, storage="f32", **lattice_kw):
     """Run the learned-curvature step on the GPU and in the FP64 oracle; the
     bars as in test_step_with_learned_curvature_matches_oracle (the network
     output difference e_net times the network's share of the flow)."""
     import torch
 
     print(f"case {label}", flush=True)
-    g = lbm.Lattice(shape, 0.8, phi0=phi0, u0=u0, curv_mode="mlp", **lattice_kw, **kw)
+    g = lbm.Lattice(shape, 0.8, phi0=phi0, u0=u0, curv_mode="mlp", storage=storage, **lattice_kw, **kw)
     g.set_mlp(torch.tensor(w.astype(np.float16).view(np.int16), device="cuda"))
     g.step(steps)
     m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
@@ -262,8 +262,9 @@ def _learned_vs_oracle(lbm, shape, phi0, u0, w, kw, steps, label, **lattice_kw):
     dfd = np.linalg.norm(mfd["u"] - mo["u"]) / np.linalg.norm(mo["u"])
     dfd_p = np.abs(mfd["p"] - mo["p"]).max() / np.abs(mo["p"] - mo["p"].mean()).max()
     print(f"{label}: network outputs differ by {e_net:.3e} on {n} cells; FD vs learned oracle runs by {dfd:.3e}")
-    check(m, mo, "f32", label, u_bar=1e-5 + 2.0 * e_net * dfd, p_bar=1e-5 + 2.0 * e_net_max * dfd_p,
-          phi_bar=1e-5, drho=kw["rho_l"] - kw["rho_g"])
+    ub = U_BAR[storage]
+    check(m, mo, storage, label, u_bar=ub + 2.0 * e_net * dfd, p_bar=ub + 2.0 * e_net_max * dfd_p,
+          phi_bar=ub, drho=kw["rho_l"] - kw["rho_g"])
     assert dfd > 1e-4 and n > 50
 
 
@@ -297,3 +298,19 @@ def test_learned_curvature_in_a_thin_box_with_ragged_z_chunks_matches_oracle():
     kw = dict(rho_l=1.0, rho_g=0.5, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
     _learned_vs_oracle(lbm, shape, phi0, u0, _mlp_case_weights(35), kw, 40,
                        "learned curvature, nz = 8, z-chunks 3 3 2", zchunk=3)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_learned_curvature_with_16bit_populations_matches_oracle(storage):
+    """The learned-curvature step with FP16 and BF16 population storage (the
+    pass is the same; the step's 16-bit variants read its output), against
+    the FP64 oracle at the storage's bars."""
+    lbm = _lbm()
+    shape = (24, 20, 70)
+    phi_a, _ = I.droplet(shape, 3.0, 4.0, center=(20.3, 10.1, 12.2))
+    phi_b, _ = I.droplet(shape, 4.0, 4.0, center=(52.7, 9.6, 11.4))
+    phi0 = np.maximum(phi_a, phi_b)
+    u0 = I.random_u(shape, 0.005, seed=43)
+    kw = dict(rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05, width=4.0, p0=0.0)
+    _learned_vs_oracle(lbm, shape, phi0, u0, _mlp_case_weights(36), kw, 30, f"learned curvature, {storage} populations",
+                       storage=storage, zchunk=8)
