@@ -415,39 +415,44 @@ def hit_report(steps=20000, every=2000, n=256, oracle_n=64, oracle_checks=(250, 
 
 def oracle_timing():
     """The FP64 oracle on the host cores for the four benchmark workloads:
-    TGV 32^3 (200 steps), static droplet 64^3 (R = 12, ratio 10;
-    the first 500 of its 5000 steps), single-phase forced HIT 256^3 (20 steps),
-    512^3 bubbly HIT (2 steps).  Prints one line per workload as it finishes
-    and returns MLUPS per workload."""
+    TGV 32^3 (200 steps), static droplet 64^3 (R = 12, ratio 10, all 5000
+    steps of the configuration), single-phase forced HIT 256^3 (100 steps),
+    512^3 bubbly HIT (3 blocks of 10 steps, median).  Each after one untimed
+    step; prints a line per block of steps as it goes and returns MLUPS per
+    workload."""
     import oracle as O
     from paper_2505_01126_amd import inputs as I
 
     out = {}
 
-    def run(name, o, steps, chunk):
+    def run(name, o, steps, chunk, repeats=1):
         o.step(1)
-        t0 = time.perf_counter()
-        done = 0
-        while done < steps:
-            k = min(chunk, steps - done)
-            o.step(k)
-            done += k
-            print(f"# oracle {name}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-                  flush=True)
-        dt = time.perf_counter() - t0
-        out[name] = {"mlups": o.N * steps / dt / 1e6, "steps": steps, "seconds": dt}
+        blocks = []
+        for r in range(repeats):
+            t0 = time.perf_counter()
+            done = 0
+            while done < steps:
+                k = min(chunk, steps - done)
+                o.step(k)
+                done += k
+                print(f"# oracle {name} (block {r + 1}/{repeats}): {done}/{steps} steps, "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            blocks.append(time.perf_counter() - t0)
+        dt = float(np.median(blocks))
+        out[name] = {"mlups": o.N * steps / dt / 1e6, "steps": steps, "seconds": dt, "blocks": len(blocks),
+                     "block_seconds": blocks}
 
     u, p, _ = I.tgv((32, 32, 32), 0.02)
     run("tgv_32", O.Oracle((32, 32, 32), 0.8, u0=u, pstar0=p), 200, 100)
     phi0, _ = I.droplet((64, 64, 64), 12.0, 4.0, seed=1)
     run("droplet_64", O.Oracle((64, 64, 64), 1.0, phi0=phi0, rho_l=1.0, rho_g=0.1, sigma=0.01, mobility=0.05,
-                               width=4.0, p0=0.0), 500, 100)
+                               width=4.0, p0=0.0), 5000, 250)
     shape = (256, 256, 256)
     u0 = I.solenoidal_field(shape, rms=0.02, k0=4.0, seed=1)
-    run("hit_256", O.Oracle(shape, 0.55, u0=u0, modes=I.forcing_modes(1e-5, seed=2)), 20, 2)
+    run("hit_256", O.Oracle(shape, 0.55, u0=u0, modes=I.forcing_modes(1e-5, seed=2)), 100, 5)
     del u0
     shape, phi0, u0, params, nb = workload(512)
-    run("bubbly_hit_512", O.Oracle(shape, 0.515, phi0=phi0, u0=u0, **params), 2, 1)
+    run("bubbly_hit_512", O.Oracle(shape, 0.515, phi0=phi0, u0=u0, **params), 10, 1, repeats=3)
     return {"cores": O.threads(), "nproc": os.cpu_count(), "workloads": out}
 
 
