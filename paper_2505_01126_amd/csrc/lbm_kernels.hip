@@ -65,7 +65,10 @@ __global__ void __launch_bounds__(NTHREADS) k_init(Params P, void *fout_, void *
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) hA += (c[a] * c[b] - (a == b ? 1.0 / 3.0 : 0.0)) * A[a][b];
         const double h = dp + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2 + 4.5 * hA;
-        fout[pop_index(P, i, nb(-CX(i), -CY(i), -CZ(i)))] = Pop<S>::enc((float)h);
+        // slot of x - c_i in the plane-major layout
+        const size_t slot = ((size_t)wrapi(z - CZ(i), nz) * 27 + i) * plane +
+                            (uint32_t)wrapi(y - CY(i), ny) * nx + (uint32_t)wrapi(x - CX(i), nx);
+        fout[slot] = Pop<S>::enc((float)h);
     }
     if (phi_out) {
         const double ph = P.two_phase ? phi0[s] : 0.0;
@@ -91,9 +94,15 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t plane = (uint32_t)nx * ny, N = plane * (uint32_t)nz;
     const int x = s % nx, y = (s / nx) % ny, z = s / plane;
-    auto nb = [&](int dx, int dy, int dz) {
-        return (uint32_t)wrapi(z + dz, nz) * plane + (uint32_t)wrapi(y + dy, ny) * nx + (uint32_t)wrapi(x + dx, nx);
+    // the periodic neighbours' coordinates, once per site: index k = 1 + offset
+    const uint32_t xk[3] = {(uint32_t)wrapi(x - 1, nx), (uint32_t)x, (uint32_t)wrapi(x + 1, nx)};
+    const uint32_t yk[3] = {(uint32_t)wrapi(y - 1, ny) * nx, (uint32_t)y * nx, (uint32_t)wrapi(y + 1, ny) * nx};
+    const uint32_t zk[3] = {(uint32_t)wrapi(z - 1, nz), (uint32_t)z, (uint32_t)wrapi(z + 1, nz)};
+    // population i of site s + d (plane-major layout) and the phase field there
+    auto pop_at = [&](int i, int dx, int dy, int dz) {
+        return ((size_t)zk[1 + dz] * 27 + i) * plane + yk[1 + dy] + xk[1 + dx];
     };
+    auto site_at = [&](int dx, int dy, int dz) { return zk[1 + dz] * plane + yk[1 + dy] + xk[1 + dx]; };
     M10 M;
     PhiGrad G;
     float ph[27];
@@ -102,11 +111,11 @@ __device__ __forceinline__ void site_state(const Params &P, const void *fin_, co
     if (valid) {
         float hv[27];
 #pragma unroll
-        for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[pop_index(P, i, nb(-CX(i), -CY(i), -CZ(i)))]);
+        for (int i = 0; i < 27; i++) hv[i] = Pop<S>::dec(fin[pop_at(i, -CX(i), -CY(i), -CZ(i))]);
         moments10(hv, M);
         if constexpr (TP) {
 #pragma unroll
-            for (int i = 0; i < 27; i++) ph[i] = (float)phi_load(phi, nb(CX(i), CY(i), CZ(i)), P.phi_fix);
+            for (int i = 0; i < 27; i++) ph[i] = (float)phi_load(phi, site_at(CX(i), CY(i), CZ(i)), P.phi_fix);
             phi_stencil(ph, G);
             if constexpr (ML) sel = mlp_select(G, P, kfd, gn);
         }

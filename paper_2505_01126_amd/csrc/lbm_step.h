@@ -92,14 +92,6 @@ __device__ __forceinline__ int modi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// element index of population i at site s (plane-major population layout)
-__device__ __forceinline__ size_t pop_index(const Params &P, int i, uint32_t s)
-{
-    const uint32_t plane = (uint32_t)P.nx * P.ny;
-    const uint32_t z = s / plane, xy = s - z * plane;
-    return ((size_t)z * 27 + i) * plane + xy;
-}
-
 // element at a 32-bit byte offset from a uniform base: lets the compiler use
 // the scalar-base + 32-bit vector-offset addressing of global memory
 template <class T> __device__ __forceinline__ T ldb(const void *base, uint32_t byte_off)
