@@ -92,17 +92,6 @@ __device__ __forceinline__ int modi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// element at a 32-bit byte offset from a uniform base: lets the compiler use
-// the scalar-base + 32-bit vector-offset addressing of global memory
-template <class T> __device__ __forceinline__ T ldb(const void *base, uint32_t byte_off)
-{
-    return *(const T *)((const char *)base + byte_off);
-}
-template <class T> __device__ __forceinline__ void stb(void *base, uint32_t byte_off, T v)
-{
-    *(T *)((char *)base + byte_off) = v;
-}
-
 // Pointers into global memory.  Kernel arguments are known to be global; a
 // pointer read from a descriptor table (the batch kernel) is generic, and
 // generic (flat) accesses also count against the LDS wait counter, so every
@@ -114,6 +103,13 @@ template <class T> __device__ __forceinline__ const LBM_GLOBAL T *gconst(const T
     return (const LBM_GLOBAL T *)p;
 }
 template <class T> __device__ __forceinline__ LBM_GLOBAL T *gmut(T *p) { return (LBM_GLOBAL T *)p; }
+// Element at a 32-bit byte offset from a wave-uniform base (a plane of a
+// field): the scalar-base + 32-bit vector-offset form of a global load, with
+// no 64-bit address arithmetic per lane.
+template <class T> __device__ __forceinline__ T ldg(const LBM_GLOBAL T *base, uint32_t byte_off)
+{
+    return *(const LBM_GLOBAL T *)((const LBM_GLOBAL char *)base + byte_off);
+}
 
 // Phase-field storage of the step: FP64 (fluxes summed in FP64), or int32
 // fixed point q = phi 2^30 (each flux rounded to nearest on that grid, summed
@@ -172,6 +168,11 @@ template <class T> __device__ __forceinline__ void gstore(LBM_GLOBAL T *p, T v, 
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
+}
+// gstore at a 32-bit byte offset from a wave-uniform base (see ldg)
+template <class T> __device__ __forceinline__ void gstb(LBM_GLOBAL T *base, uint32_t byte_off, T v, bool nt)
+{
+    gstore((LBM_GLOBAL T *)((LBM_GLOBAL char *)base + byte_off), v, nt);
 }
 
 // ------------------------------------------------------ separable moments
@@ -581,8 +582,6 @@ template <int TW> struct Tile {
     static constexpr int QPTS = (QPLANE + NTHREADS - 1) / NTHREADS;
     static constexpr int NXF = Y * (X + 1);       // x faces of a plane tile (left of each site + 1)
     static constexpr int NYF = (Y + 1) * X;       // y faces
-    static constexpr int NFACE = NXF + NYF;
-    static constexpr int FROUNDS = (NFACE + NTHREADS - 1) / NTHREADS;
 };
 
 __device__ __forceinline__ int ring(int z) { return (z + 4 * NRING) % NRING; }
@@ -627,8 +626,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     using AT = typename PS::Acc;
     using TL = Tile<TW>;
     constexpr int TXW = TL::X, TYW = TL::Y, PX = TL::PX, PLANE = TL::PLANE, QX = TL::QX, QPLANE = TL::QPLANE,
-                  LOADS = TL::LOADS, QPTS = TL::QPTS, NXF = TL::NXF, NYF = TL::NYF, NFACE = TL::NFACE,
-                  FROUNDS = TL::FROUNDS;
+                  LOADS = TL::LOADS, QPTS = TL::QPTS, NXF = TL::NXF, NYF = TL::NYF;
     // Where the next plane's populations are fetched: 16-bit values pack two
     // to a register, so FP16/BF16 fetch right after the moments (longest
     // prefetch distance) and still fit three waves per SIMD; FP32 fetches after
@@ -717,11 +715,19 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     __shared__ float sjx[AC ? NXF : 1];
     __shared__ float sjy[AC ? NYF : 1];
     __shared__ uint32_t sxy[TP ? PLANE : 1];
+    const int lc = (ty + HY) * PX + (tx + HX);  // own phi tile index
+    const int qc = (ty + 1) * QX + (tx + 1);    // own Q tile index
     int q_lds[QPTS];
-    int f_c[FROUNDS];       // phi tile index of the left cell of this thread's faces
-    bool f_isx[FROUNDS];
     PT phn[LOADS];          // prefetched phi plane
-    float f_ul[FROUNDS], f_ur[FROUNDS];  // prefetched face velocities
+    // The x and y faces of a plane tile are evaluated in three rounds, each
+    // wave taking one direction in each: (A) the x face left of every site,
+    // (B) the y face below every site, (C) the y faces above the top row
+    // (threads 0 .. TXW-1, the first wave) and the x faces right of the last
+    // column (threads 64 .. 64+TYW-1, the second wave).  c_lc: the phi tile
+    // index of the left (lower) cell of a round-C face.
+    const bool c_top = tid < TXW, c_right = tid >= 64 && tid < 64 + TYW;
+    const int c_lc = c_top ? (TYW - 1 + HY) * PX + tid + HX : (tid - 64 + HY) * PX + (TXW - 1 + HX);
+    float fa_l, fa_r, fb_l, fb_r, fc_l = 0.f, fc_r = 0.f;  // prefetched face velocities
     float jz_left = 0.f, uz_c = 0.f, uz_n = 0.f;
     PT po = 0;              // prefetched own phi
 
@@ -741,17 +747,20 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             if (e < PLANE) dst[e] = PS::f32(phn[k]);
         }
     };
+    // (64-bit per-lane addresses: the scalar-base form of ldg made these loads
+    // cost the FP32 step 0.8 %)
     auto fetch_face_u = [&](int z) {
         const uint32_t zo = (uint32_t)z * plane;
-#pragma unroll
-        for (int k = 0; k < FROUNDS; k++) {
-            const int t = tid + k * NTHREADS;
-            if (t < NFACE) {
-                const int c = f_c[k], st = f_isx[k] ? 1 : PX;
-                const LBM_GLOBAL float *ub = f_isx[k] ? ux_in : uy_in;
-                f_ul[k] = ub[zo + sxy[c]];
-                f_ur[k] = ub[zo + sxy[c + st]];
-            }
+        fa_l = ux_in[zo + src_xy[5]];
+        fa_r = ux_in[zo + own_xy];
+        fb_l = uy_in[zo + src_xy[7]];
+        fb_r = uy_in[zo + own_xy];
+        if (c_top) {
+            fc_l = uy_in[zo + sxy[c_lc]];
+            fc_r = uy_in[zo + sxy[c_lc + PX]];
+        } else if (c_right) {
+            fc_l = ux_in[zo + sxy[c_lc]];
+            fc_r = ux_in[zo + sxy[c_lc + 1]];
         }
     };
     auto compute_q = [&](int z) {
@@ -781,20 +790,23 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
     // (f = 0..TXW), y face r of column x between tile rows r-1 and r (r = 0..TYW)
     auto compute_faces = [&](int z) {
         const float *pl = sphi[ring(z)];
-#pragma unroll
-        for (int k = 0; k < FROUNDS; k++) {
-            const int t = tid + k * NTHREADS;
-            if (t < NFACE) {
-                const int c = f_c[k], st = f_isx[k] ? 1 : PX;
-                float *out = f_isx[k] ? sjx + t : sjy + (t - NXF);
-                *out = face_flux(pl[c - 2 * st], pl[c - st], pl[c], pl[c + st], pl[c + 2 * st], pl[c + 3 * st],
-                                 f_ul[k], f_ur[k]);
-            }
+        {
+            const float *p = pl + lc - 3;  // cells x-3 .. x+2 of the row
+            sjx[ty * (TXW + 1) + tx] = face_flux(p[0], p[1], p[2], p[3], p[4], p[5], fa_l, fa_r);
+        }
+        {
+            const float *p = pl + lc - 3 * PX;  // cells y-3 .. y+2 of the column
+            sjy[ty * TXW + tx] = face_flux(p[0], p[PX], p[2 * PX], p[3 * PX], p[4 * PX], p[5 * PX], fb_l, fb_r);
+        }
+        if (c_top) {
+            const float *p = pl + c_lc - 2 * PX;
+            sjy[TYW * TXW + tid] = face_flux(p[0], p[PX], p[2 * PX], p[3 * PX], p[4 * PX], p[5 * PX], fc_l, fc_r);
+        } else if (c_right) {
+            const float *p = pl + c_lc - 2;
+            sjx[(tid - 64) * (TXW + 1) + TXW] = face_flux(p[0], p[1], p[2], p[3], p[4], p[5], fc_l, fc_r);
         }
     };
 
-    const int lc = (ty + HY) * PX + (tx + HX);  // own phi tile index
-    const int qc = (ty + 1) * QX + (tx + 1);    // own Q tile index
 
     if constexpr (TP) {
 #pragma unroll
@@ -809,20 +821,6 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             const int qy = p / QX, qx = p - qy * QX;
             q_lds[k] = (qy + 2) * PX + (qx + 2);  // phi tile centre of Q point (qx, qy)
         }
-#pragma unroll
-        for (int k = 0; k < FROUNDS; k++) {
-            const int t = tid + k * NTHREADS;
-            if (t < NXF) {
-                const int r = t / (TXW + 1), f = t - r * (TXW + 1);
-                f_c[k] = (r + HY) * PX + (f - 1 + HX);
-                f_isx[k] = true;
-            } else {
-                const int t2 = t - NXF;
-                const int r = t2 / TXW, xx = t2 - r * TXW;
-                f_c[k] = (r - 1 + HY) * PX + (xx + HX);
-                f_isx[k] = false;
-            }
-        }
         for (int z = z0 - 3; z <= z0 + 2; z++) {
             fetch_plane(z);
             store_plane(z);
@@ -836,7 +834,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
             // z face below the first plane: cells z0-3 .. z0+2, velocities at z0-1, z0
             const float um = uz_in[(uint32_t)modi(z0 - 1, nz) * plane + own_xy];
             uz_c = uz_in[(uint32_t)z0 * plane + own_xy];
-            uz_n = uz_in[(uint32_t)wrapi(z0 + 1, nz) * plane + own_xy];
+            uz_n = ldg(uz_in + (size_t)wrapi(z0 + 1, nz) * plane, own_xy * 4u);
             po = phin[(size_t)z0 * plane + own_xy];
             float v[6];
 #pragma unroll
@@ -897,7 +895,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                     acc[1] = PS::flux(jz_left) - PS::flux(jr);
                     jz_left = jr;
                     uz_c = uz_n;
-                    uz_n = uz_in[(uint32_t)wrapi(zn + 1, nz) * plane + own_xy];
+                    uz_n = ldg(uz_in + (size_t)wrapi(zn + 1, nz) * plane, own_xy * 4u);
                 }
                 {
                     // phase-field stencil of this site (LDS)
@@ -938,7 +936,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                            rk_b * (po + ((acc[0] + acc[1]) + (acc[2] + acc[3])));
                 else
                     pnew = PS::add(po, (acc[0] + acc[1]) + (acc[2] + acc[3]));
-                gstore(&phout[(size_t)own], pnew, nt_rows && !ACO);
+                gstb(phout + (size_t)z * plane, own_xy * (uint32_t)sizeof(PT), pnew, nt_rows && !ACO);
                 if constexpr (ML || ACO) {
                     // interface flags of the new phi, as the next network pass
                     // will see it (its FP32 value): one byte per 32-lane half
@@ -952,7 +950,7 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                                 (uint8_t)(((lane < 32 ? m : m >> 32) & 0xffffffffull) != 0);
                     }
                 }
-                po = phin[(size_t)zn * plane + own_xy];
+                po = ldg(phin + (size_t)zn * plane, own_xy * (uint32_t)sizeof(PT));
             }
             // Every other load of this plane is issued before the populations of
             // the next one: loads complete in order, so waiting for a load
@@ -1005,9 +1003,9 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                 store_pops(std::integral_constant<int, 0>{});
 
             if constexpr (TP) {  // velocity of this step, advects phi in the next one
-                gstore(&uout[own], m.u[0], nt_rows);
-                gstore(&uout[(size_t)N + own], m.u[1], nt_rows);
-                gstore(&uout[2 * (size_t)N + own], m.u[2], nt_rows);
+                gstb(uout + (size_t)z * plane, own_xy * 4u, m.u[0], nt_rows);
+                gstb(uout + (size_t)N + (size_t)z * plane, own_xy * 4u, m.u[1], nt_rows);
+                gstb(uout + 2 * (size_t)N + (size_t)z * plane, own_xy * 4u, m.u[2], nt_rows);
             }
         }
     }
