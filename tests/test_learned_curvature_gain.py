@@ -19,7 +19,13 @@ random cube symmetries.  It is evaluated on spheres it has not seen:
    learned blend on the ramp |K_FD| from 0.2 to 0.3, against the
    finite-difference run, at density ratio 1 and 10, with a bound on the
    spurious currents.  R = 2.5 is printed, not asserted: there the blend loses
-   to finite differences at both density ratios.
+   to finite differences at both density ratios;
+3. the same at the benchmark's fluid (tau = 0.515, sigma = 0.005) with the
+   library's ramp (0.4 to 0.6), 3000 steps, the pressure averaged over the
+   last 200: the blend wins at R = 4 and 6.
+   At R = 3 it is printed, not asserted: per-cell errors of the network's K
+   and normal make the surface-tension force partly solenoidal, and at this
+   viscosity the currents that drives stir small droplets apart.
 
 Parity of the kernels themselves is covered by test_gpu_mlp.py.
 """
@@ -76,25 +82,34 @@ def test_learned_curvature_carries_the_laplace_jump_of_unseen_spheres(trained):
     assert e_net < 0.5 * e_fd
 
 
-def _laplace(mode, R, ratio, w16, n=32, steps=1500):
+def _laplace(mode, R, ratio, w16, n=32, steps=1500, tau=1.0, sigma=SIGMA, ramp=(K_LO, K_HI), window=1):
+    """Laplace error and max|u| after `steps`; with window > 1 the pressure is
+    averaged over `window` snapshots 20 steps apart ending there (at low
+    viscosity the pressure oscillates for thousands of steps)."""
     from paper_2505_01126_amd import lbm
 
     phi0, c = I.droplet((n, n, n), R, 4.0, seed=int(R * 10))
-    print(f"case Laplace {mode} R={R} ratio={ratio}", flush=True)
-    g = lbm.Lattice((n, n, n), 1.0, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=SIGMA, mobility=0.05,
-                    width=4.0, p0=0.0, curv_mode=mode, mlp_k_lo=K_LO, mlp_k_hi=K_HI)
+    print(f"case Laplace {mode} R={R} ratio={ratio} tau={tau} sigma={sigma} ramp={ramp}", flush=True)
+    g = lbm.Lattice((n, n, n), tau, phi0=phi0, rho_l=1.0, rho_g=1.0 / ratio, sigma=sigma, mobility=0.05,
+                    width=4.0, p0=0.0, curv_mode=mode, mlp_k_lo=ramp[0], mlp_k_hi=ramp[1])
     if mode == "mlp":
         g.set_mlp(w16)
-    g.step(steps)
-    m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+    g.step(steps - 20 * (window - 1))
+    ps, umax = [], 0.0
+    for j in range(window):
+        if j:
+            g.step(20)
+        m = {k: v.double().cpu().numpy() for k, v in g.moments().items()}
+        ps.append(m["p"])
+        umax = max(umax, float(np.abs(m["u"]).max()))
     g.close()
-    phi, p = m["phi"], m["p"]
+    phi, p = m["phi"], np.mean(ps, axis=0)
     reff = (3.0 * phi.sum() / (4.0 * math.pi)) ** (1.0 / 3.0)
     z, y, x = I.grid((n, n, n))
     d = np.sqrt(((x - c[0] + n / 2) % n - n / 2) ** 2 + ((y - c[1] + n / 2) % n - n / 2) ** 2 +
                 ((z - c[2] + n / 2) % n - n / 2) ** 2)
     dp = p[d < 1.5].mean() - p[d > R + 12].mean()
-    return dp / (2.0 * SIGMA / reff) - 1.0, np.abs(m["u"]).max()
+    return dp / (2.0 * sigma / reff) - 1.0, umax
 
 
 @pytest.mark.parametrize("ratio", [1.0, 10.0])
@@ -108,3 +123,15 @@ def test_learned_curvature_improves_laplace_law(trained, ratio):
             assert abs(enet) < abs(efd)
         # spurious currents: bounded against the FD run and the capillary velocity
         assert unet < 25.0 * ufd and unet < 0.1 * CAPILLARY_U
+
+
+@pytest.mark.parametrize("ratio", [1.0, 10.0])
+def test_learned_curvature_at_low_viscosity(trained, ratio):
+    for R in (3.0, 4.0, 6.0):
+        kw = dict(steps=3000, tau=0.515, sigma=0.005, ramp=(0.4, 0.6), window=10)
+        efd, ufd = _laplace("fd", R, ratio, None, **kw)
+        enet, unet = _laplace("mlp", R, ratio, trained.w16, **kw)
+        print(f"tau 0.515, ratio {ratio:g} R {R:g}: Laplace error FD {efd:+.4f} (max|u| {ufd:.1e}), "
+              f"learned {enet:+.4f} (max|u| {unet:.1e}, {unet / ufd:.1f}x FD)")
+        if R >= 4.0:
+            assert abs(enet) < abs(efd)
