@@ -1,12 +1,12 @@
 """What the learned curvature gains over the finite-difference curvature.
 
 The network (27 -> 64 -> 64 -> 4, FP16 MFMA training kernels) is trained with
-train_curvature's default recipe: 48 periodic 48^3 boxes of 4 droplets or
+train_curvature's default recipe: 96 periodic 48^3 boxes of 4 droplets or
 bubbles with radii in [2, 10] (1/R uniform, so small spheres contribute as
 many interface cells as large ones), relaxed by the coupled solver and
 harvested with the Laplace-consistent curvature label K = (2 / R_eff) / I (I
 the integral of the surface-tension profile across the relaxed sphere);
-4000 Adam steps on rows drawn in proportion to |grad phi|^2 and turned by
+32000 Adam steps of 16384 rows drawn in proportion to |grad phi|^2 and turned by
 random cube symmetries.  It is evaluated on spheres it has not seen:
 
 1. the Laplace jump that the surface-tension force of Eq. (8) carries across
@@ -22,10 +22,10 @@ random cube symmetries.  It is evaluated on spheres it has not seen:
    to finite differences at both density ratios;
 3. the same at the benchmark's fluid (tau = 0.515, sigma = 0.005) with the
    library's ramp (0.4 to 0.6), 3000 steps, the pressure averaged over the
-   last 200: the blend wins at R = 4 and 6.
-   At R = 3 it is printed, not asserted: per-cell errors of the network's K
-   and normal make the surface-tension force partly solenoidal, and at this
-   viscosity the currents that drives stir small droplets apart.
+   last 200: the blend wins at R = 4 and 6, and at R = 3 for density ratio
+   10.  R = 3 at ratio 1 is printed, not asserted (there it loses): per-cell
+   errors of the network's K and normal make the surface-tension force
+   partly solenoidal, and at this viscosity the currents that drives matter.
 
 Parity of the kernels themselves is covered by test_gpu_mlp.py.
 """
@@ -133,5 +133,5 @@ def test_learned_curvature_at_low_viscosity(trained, ratio):
         enet, unet = _laplace("mlp", R, ratio, trained.w16, **kw)
         print(f"tau 0.515, ratio {ratio:g} R {R:g}: Laplace error FD {efd:+.4f} (max|u| {ufd:.1e}), "
               f"learned {enet:+.4f} (max|u| {unet:.1e}, {unet / ufd:.1f}x FD)")
-        if R >= 4.0:
+        if R >= 4.0 or ratio == 10.0:
             assert abs(enet) < abs(efd)
