@@ -53,10 +53,14 @@ __host__ __device__ constexpr double WTD(int i)
 
 // ----------------------------------------------------------------- storage
 template <int S> struct Pop;
+// enc: round to nearest even (the initial state); enc_step: the encode of the
+// step's post-collision values, given the bits of another population of the
+// same site as a source of dither (used by BF16 only).
 template <> struct Pop<0> {
     using T = float;
     __device__ static float dec(T v) { return v; }
     __device__ static T enc(float v) { return v; }
+    __device__ static T enc_step(float v, uint32_t) { return v; }
 };
 template <> struct Pop<1> {
     using T = _Float16;
@@ -71,6 +75,7 @@ template <> struct Pop<1> {
         asm("v_cvt_f16_f32 %0, %1" : "=v"(r) : "v"(v));
         return __builtin_bit_cast(T, (uint16_t)r);
     }
+    __device__ static T enc_step(float v, uint32_t) { return enc(v); }
 };
 template <> struct Pop<2> {
     using T = __bf16;
@@ -82,6 +87,21 @@ template <> struct Pop<2> {
         uint32_t r;
         asm("v_cvt_pk_bf16_f32 %0, %1, 0" : "=v"(r) : "v"(v));
         return __builtin_bit_cast(T, (uint16_t)r);
+    }
+    // Stochastic rounding: a BF16 ulp of a shifted population (|h| ~ 0.03) is
+    // about 1e-4, far above the change that a weak body force makes in one
+    // step, so rounding to nearest drops that change at every step and the
+    // flow drifts.  Adding 16 dither bits below the kept mantissa before
+    // cutting them off rounds up with probability equal to the cut fraction,
+    // so the change survives in expectation.  The dither is the low 16 bits
+    // of another population of the site (their low mantissa bits are close to
+    // uniform): deterministic, with no state, the same bits in every kernel
+    // variant.  A NaN stays a NaN; a value within a dither of the largest
+    // finite one may round to infinity.
+    __device__ static T enc_step(float v, uint32_t dither)
+    {
+        const uint32_t b = __builtin_bit_cast(uint32_t, v) + (dither & 0xffffu);
+        return __builtin_bit_cast(T, (uint16_t)(b >> 16));
     }
 };
 
@@ -992,7 +1012,8 @@ __device__ __forceinline__ void step_tile(const Params &P, const Buffers &B, con
                 uint32_t soff = 0;
 #pragma unroll
                 for (int i = 0; i < 27; i++) {
-                    bstore<T, decltype(aux)::value>(dst, own_xy * ES, soff, Pop<S>::enc(h[i]));
+                    bstore<T, decltype(aux)::value>(dst, own_xy * ES, soff,
+                                                    Pop<S>::enc_step(h[i], __builtin_bit_cast(uint32_t, h[(i + 1) % 27])));
                     soff += plane * ES;
                     asm volatile("" : "+s"(soff));
                 }
