@@ -52,7 +52,11 @@ enum {
 };
 
 /* population storage: FP32, or FP16 / BF16 holding h_i = f_i / w_i - P0
- * (arithmetic is FP32 in every mode; FP32 storage holds the same shifted h_i) */
+ * (arithmetic is FP32 in every mode; FP32 storage holds the same shifted h_i).
+ * FP16 rounds to nearest even.  BF16 rounds the step's stores stochastically
+ * (dither: the low 16 bits of another population of the same site, so the
+ * result is deterministic), which keeps a weak body force's per-step change
+ * that rounding to nearest would drop; lbm_init rounds to nearest. */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
 
 /* phase-field storage (two-phase runs; the arithmetic is FP32 in both):
