@@ -586,8 +586,8 @@ def main():
                     help="only run 10 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the z-slab multi-GPU layout is described in the design notes but not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(there is no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     if args.oracle_timing:
