@@ -1062,16 +1062,36 @@ __device__ __forceinline__ void pass_tile(const Params &P, const Buffers &B, con
     // lanes past a ragged box edge evaluate the periodic image of their site
     // and write the owner's bits again
     const int xg = (x0 + tx) % nx, yg = (y0 + ty) % ny;
+    // planes zs .. ze-1 of the chunk hold every interface cell of the item:
+    // the first and last planes with a flag set (a candidate cell of plane z
+    // sets its segment's flag of plane z)
+    int zs = z0, ze = zend;
     if (B.iflag) {
+        __shared__ int s_kmin, s_kmax;
         const int nseg = flag_segments(nx);
         const int s0 = x0 / 32, ns = min((x0 + TXW + 31) / 32, nseg) - s0;
         const int nr = min(TYW, ny - y0), np = zend - z0;
-        bool any = false;
+        if (tid == 0) {
+            s_kmin = np;
+            s_kmax = -1;
+        }
+        __syncthreads();
+        int kmin = np, kmax = -1;
         for (int e = tid; e < ns * nr * np; e += NTHREADS) {
             const int si = e % ns, r = (e / ns) % nr, k = e / (ns * nr);
-            any |= B.iflag[((size_t)(z0 + k) * ny + (y0 + r)) * nseg + s0 + si] != 0;
+            if (B.iflag[((size_t)(z0 + k) * ny + (y0 + r)) * nseg + s0 + si] != 0) {
+                kmin = min(kmin, k);
+                kmax = max(kmax, k);
+            }
         }
-        if (!__syncthreads_or(any)) return;
+        if (kmax >= 0) {
+            atomicMin(&s_kmin, kmin);
+            atomicMax(&s_kmax, kmax);
+        }
+        __syncthreads();
+        if (s_kmax < 0) return;  // uniform: no interface cell in the item
+        zs = z0 + s_kmin;
+        ze = z0 + s_kmax + 1;
     }
     if (P.mlp != loaded) {  // uniform: one box per work item
         load_weights(gconst((const uint16_t *)P.mlp), W, tid, NTHREADS);
@@ -1150,21 +1170,21 @@ __device__ __forceinline__ void pass_tile(const Params &P, const Buffers &B, con
         store_plane(r, z + 1);
         fetch_plane(r, z + 4);
         lds_barrier();
-        if (z < zend) compute(z);
+        if (z < ze) compute(z);
     };
-    fetch_plane(ra, z0 - 1);
-    store_plane(ra, z0 - 1);
-    fetch_plane(ra, z0);
-    store_plane(ra, z0);
+    fetch_plane(ra, zs - 1);
+    store_plane(ra, zs - 1);
+    fetch_plane(ra, zs);
+    store_plane(ra, zs);
     // issued in this order (the compiler would otherwise reorder the three
     // sets, and the first wait of every pass through the loop would then
     // cover all of them)
-    fetch_plane(ra, z0 + 1);
+    fetch_plane(ra, zs + 1);
     asm volatile("" ::: "memory");
-    fetch_plane(rb, z0 + 2);
+    fetch_plane(rb, zs + 2);
     asm volatile("" ::: "memory");
-    fetch_plane(rc, z0 + 3);
-    for (int z = z0; z < zend; z += 3) {
+    fetch_plane(rc, zs + 3);
+    for (int z = zs; z < ze; z += 3) {
         plane_step(z, ra);
         plane_step(z + 1, rb);
         plane_step(z + 2, rc);
